@@ -1,0 +1,188 @@
+/*
+ * lb.h -- C ABI of the MI355X (gfx950) D2Q37 thermal lattice Boltzmann step.
+ *
+ * Method: Calore, Gabbana, Kraus, Schifano, Tripiccione, "Performance and
+ * Portability of Accelerated Lattice Boltzmann Applications with OpenACC".
+ * One time step is, as in Sec. 2: propagate (each of the 37 populations is
+ * gathered from the site e_l away, |e_l| up to 3 sites, Eq. (1) left side),
+ * bc (top and bottom walls at fixed temperature and zero velocity), collide
+ * (Eq. (2) moments, equilibrium, relaxation with rate 1/tau, Hermite
+ * projection, gravity).  x is periodic through three halo columns on each side
+ * (Sec. 2 and Sec. 4).
+ *
+ * Units.  Populations hop by integer vectors e_l; their lattice velocities are
+ * c_l = r e_l (r = 1.19697977..., fixed by the degree-9 quadrature), so T = 1
+ * is the reference temperature and u, T and g below are in the units of c_l
+ * with a time step of 1.
+ *
+ * Conventions for every entry point.
+ *  - All functions return an int status: LB_OK (0) or a negative LB_E_* code.
+ *    lb_last_error() returns a thread-local, human-readable message for the
+ *    last failure on the calling thread.
+ *  - Device pointers are plain device addresses (e.g. torch tensor data_ptr()).
+ *    The caller owns ALL device memory, including the workspace; the library
+ *    owns only the host-side lb_ctx (freed by lb_free).
+ *  - Fields (rho, ux, uy, T, gradients) are FP64, x-major [lx][ly], contiguous
+ *    (y fastest).  Population arrays in the compact form are [37][lx][ly].
+ *  - Work is enqueued asynchronously on the stream given to lb_init (a
+ *    hipStream_t passed as void*, NULL = the null stream); nothing waits for
+ *    the GPU except lb_step with check_finite > 0.  The caller synchronises
+ *    before reading results.  Errors of already-enqueued work surface as
+ *    LB_E_HIP at a later call (sticky).
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef D2Q37_LB_H
+#define D2Q37_LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LB_OK 0
+#define LB_E_ARG (-1)       /* null pointer, bad size or parameter        */
+#define LB_E_WORKSPACE (-2) /* workspace too small or misaligned          */
+#define LB_E_HIP (-3)       /* HIP runtime error (launch or earlier fault) */
+#define LB_E_STATE (-4)     /* call not valid in this context's state      */
+#define LB_E_NONFINITE (-5) /* check_finite found rho<=0, T<=0 or NaN/Inf  */
+
+/* lb_lattice.precision */
+#define LB_FP64 0         /* populations stored and collided in FP64              */
+#define LB_FP32_SHIFTED 1 /* FP32 storage of g_l = f_l - w_l rho_ref, FP32 sums,  */
+                          /* equilibrium coefficients and relaxation in FP64      */
+/* lb_lattice.ybc */
+#define LB_Y_WALLS 0    /* thermal walls below row 0 and above row ly-1 */
+#define LB_Y_PERIODIC 1 /* periodic y (no walls), for tests             */
+/* lb_lattice.layout: address of population l at padded site (X, Y) */
+#define LB_LAYOUT_SOA 0    /* l*NX*NY + X*NY + Y   (the paper's layout, Sec. 4) */
+#define LB_LAYOUT_COLUMN 1 /* X*37*NY + l*NY + Y   (all populations of a column */
+                           /*  contiguous)                                      */
+/* lb_params.kernel */
+#define LB_KERNEL_FUSED 0 /* one kernel per step: propagate+bc+collide        */
+#define LB_KERNEL_SPLIT 1 /* halo, propagate, bc, collide as separate kernels */
+
+typedef struct lb_lattice {
+  int32_t lx;        /* physical sites along x (periodic), >= 6         */
+  int32_t ly;        /* physical sites along y (walls), >= 6            */
+  int32_t precision; /* LB_FP64 or LB_FP32_SHIFTED                      */
+  int32_t ybc;       /* LB_Y_WALLS or LB_Y_PERIODIC                     */
+  int32_t layout;    /* LB_LAYOUT_SOA or LB_LAYOUT_COLUMN               */
+  int32_t reserved;  /* must be 0                                       */
+} lb_lattice;
+
+typedef struct lb_params {
+  double tau;          /* relaxation time, > 0.5 (Eq. (1))                     */
+  double gx, gy;       /* gravity (acceleration per step)                      */
+  double t_bottom;     /* wall temperature below row 0                         */
+  double t_top;        /* wall temperature above row ly-1                      */
+  double rho_ref;      /* shift density of LB_FP32_SHIFTED (ignored for FP64)  */
+  int32_t regularize;  /* 1: Hermite projection of the collision, 0: plain BGK */
+  int32_t kernel;      /* LB_KERNEL_FUSED or LB_KERNEL_SPLIT                   */
+  int32_t check_finite; /* 0: off; N > 0: every N steps lb_step scans the state */
+                        /* and returns LB_E_NONFINITE if rho<=0, T<=0 or NaN   */
+  int32_t reserved;     /* must be 0                                           */
+} lb_params;
+
+typedef struct lb_ctx lb_ctx;
+
+const char* lb_last_error(void);
+int lb_version(void);
+
+/* Bytes of device workspace lb_init needs for this lattice (two padded
+ * population buffers plus a small scratch area).  Pure host computation. */
+int lb_workspace_bytes(const lb_lattice* lat, const lb_params* par, size_t* bytes);
+
+/* Creates a context on the current HIP device.  `workspace` (device, >= the
+ * size from lb_workspace_bytes, 256-byte aligned) is carved into the state
+ * buffer A, the scratch buffer B and reduction scratch; it must outlive the
+ * context.  The state is set to the equilibrium f_l = f^eq_l(rho0, u0, T0)
+ * (Sec. 2: the run starts from an assignment of the populations at t = 0),
+ * then the halos are refreshed.  rho0, ux0, uy0, T0: device FP64 [lx][ly].
+ * Errors: LB_E_ARG (sizes < 6, tau <= 0.5, null pointers, reserved != 0),
+ * LB_E_WORKSPACE, LB_E_HIP. */
+int lb_init(const lb_lattice* lat, const lb_params* par, void* workspace,
+            size_t workspace_bytes, void* stream, const double* rho0,
+            const double* ux0, const double* uy0, const double* T0,
+            lb_ctx** out);
+
+/* Releases the host-side context (device memory belongs to the caller). */
+int lb_free(lb_ctx* ctx);
+
+/* Changes the stream later work is enqueued on. */
+int lb_set_stream(lb_ctx* ctx, void* stream);
+
+/* Replaces the physical parameters (tau, g, walls, regularize, kernel,
+ * check_finite); rho_ref cannot change after lb_init.  LB_E_ARG as lb_init. */
+int lb_set_params(lb_ctx* ctx, const lb_params* par);
+
+/* Advances the state by n >= 0 full steps (propagate -> bc -> collide),
+ * with the fused kernel or the split kernels as par->kernel selects. */
+int lb_step(lb_ctx* ctx, int n);
+
+/* Eq. (2) of the current (post-collision) state: rho = sum f,
+ * rho u = sum c f, 2 rho T = sum |c - u|^2 f, computed in FP64.  Outputs are
+ * device FP64 [lx][ly]; any of them may be NULL. */
+int lb_moments(lb_ctx* ctx, double* rho, double* ux, double* uy, double* T);
+
+/* Device copies of the state in compact form [37][lx][ly]: double for
+ * LB_FP64, float g_l = f_l - w_l rho_ref for LB_FP32_SHIFTED.  set_state
+ * refreshes the halos.  Used for checkpoints. */
+int lb_get_state(lb_ctx* ctx, void* f);
+int lb_set_state(lb_ctx* ctx, const void* f);
+
+/* The state as true populations f_l in FP64 [37][lx][ly], any precision. */
+int lb_get_populations(lb_ctx* ctx, double* f);
+
+/* Single stages of the split path, for per-kernel tests and timing.
+ *   lb_halo:      refreshes the periodic halos of the state buffer A
+ *                 (x columns; also y rows when ybc = LB_Y_PERIODIC).
+ *   lb_propagate: B(l, x, y) = A(l, x - e_lx, y - e_ly) for every physical
+ *                 site (needs valid halos); slots whose source row is outside
+ *                 the walls are left unspecified for bc.
+ *   lb_bc:        applies the thermal walls to B in place (rows 0..2 and
+ *                 ly-3..ly-1; no-op for LB_Y_PERIODIC).
+ *   lb_collide:   A = collide(B), site by site.
+ * lb_get_scratch / lb_set_scratch copy B's physical region in the compact
+ * form of lb_get_state. */
+int lb_halo(lb_ctx* ctx);
+int lb_propagate(lb_ctx* ctx);
+int lb_bc(lb_ctx* ctx);
+int lb_collide(lb_ctx* ctx);
+int lb_get_scratch(lb_ctx* ctx, void* f);
+int lb_set_scratch(lb_ctx* ctx, const void* f);
+
+/* Adjoint (LB_FP64 contexts only; LB_E_STATE otherwise).
+ *
+ * lb_step_record: like lb_step(n) with the fused kernel, and also writes, for
+ * each step j, the four pre-collision moments m = (rho, rho u_x, rho u_y,
+ * sum |c|^2 f) of every site to tape + j*4*lx*ly as [4][lx][ly] FP64.
+ *
+ * lb_loss_ke: KE = (1/2) sum rho |u|^2 of the current state into ke_dev (one
+ * device double) and, if lambda != NULL, dKE/df_l = c_l.u - |u|^2/2 into
+ * lambda [37][lx][ly].
+ *
+ * lb_adjoint_step: lambda_out = (d f^{n+1} / d f^n)^T lambda_in for the step
+ * whose pre-collision moments are tape_j ([4][lx][ly] from lb_step_record):
+ * the transposed collision, walls and propagation, in one kernel.  lambda_in
+ * and lambda_out are distinct [37][lx][ly] buffers.
+ *
+ * lb_init_adjoint: given lambda0 = dL/df^0 and the initial fields
+ * (rho0, ux0, uy0, T0) the state was built from, writes dL/d(rho0, ux0, uy0,
+ * T0) of the initial equilibrium f^0 = f^eq(rho0, u0, T0); all [lx][ly],
+ * outputs may be NULL. */
+int lb_step_record(lb_ctx* ctx, int n, double* tape);
+int lb_loss_ke(lb_ctx* ctx, double* ke_dev, double* lambda);
+int lb_adjoint_step(lb_ctx* ctx, const double* tape_j, const double* lambda_in,
+                    double* lambda_out);
+int lb_init_adjoint(lb_ctx* ctx, const double* rho0, const double* ux0,
+                    const double* uy0, const double* T0, const double* lambda0,
+                    double* drho0, double* dux0, double* duy0, double* dT0);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* D2Q37_LB_H */

@@ -100,6 +100,9 @@ def lib():
         L.oracle_moments.restype = None
         L.oracle_kinetic_energy.argtypes = [i, i, dp]
         L.oracle_kinetic_energy.restype = d
+        L.oracle_step_sites.argtypes = [i, i, pp, dp, i, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32), dp]
+        L.oracle_step_sites.restype = None
         L.oracle_ke_after_steps_complex.argtypes = [i, i, pp, dp, dp, dp, dp, i, dp]
         L.oracle_ke_after_steps_complex.restype = None
         _lib = L
@@ -197,6 +200,20 @@ def run(f, params: Params, nsteps: int) -> np.ndarray:
     _, lx, ly = out.shape
     P = params.c()
     lib().oracle_run(lx, ly, ctypes.byref(P), _p(out), int(nsteps))
+    return out
+
+
+def step_sites(f, params: Params, xs, ys) -> np.ndarray:
+    """Post-step populations [n, 37] at sites (xs[i], ys[i]) of the state f."""
+    f = _f64(f)
+    _, lx, ly = f.shape
+    xs = np.ascontiguousarray(xs, dtype=np.int32)
+    ys = np.ascontiguousarray(ys, dtype=np.int32)
+    out = np.zeros((len(xs), Q))
+    P = params.c()
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lib().oracle_step_sites(lx, ly, ctypes.byref(P), _p(f), len(xs), xs.ctypes.data_as(ip),
+                            ys.ctypes.data_as(ip), _p(out))
     return out
 
 

@@ -360,8 +360,31 @@ void propagate(int lx, int ly, int ybc, const S* f, S* ft) {
 // the same mass as what arrived.
 // ---------------------------------------------------------------------------
 template <class S>
-void boundary(int lx, int ly, double t_bottom, double t_top, S* ft) {
+void boundary_site(int y, int ly, const S* vb, const S* vt, S* ft) {
   const Model& M = model();
+  if (y >= 3 && y < ly - 3) return;
+  const S* v = (y < 3) ? vb : vt;
+  bool unknown[Q];
+  bool any = false;
+  for (int l = 0; l < Q; ++l) {
+    const int ys = y - M.cy[l];
+    unknown[l] = (ys < 0 || ys >= ly);
+    any = any || unknown[l];
+  }
+  if (!any) return;
+  S num(0.0), den(0.0);
+  for (int l = 0; l < Q; ++l)
+    if (!unknown[l]) {
+      num += ft[l];
+      den += v[l];
+    }
+  const S rho_w = num / den;
+  for (int l = 0; l < Q; ++l)
+    if (unknown[l]) ft[l] = rho_w * v[l];
+}
+
+template <class S>
+void boundary(int lx, int ly, double t_bottom, double t_top, S* ft) {
   S vb[Q], vt[Q];
   equilibrium<S>(S(1.0), S(0.0), S(0.0), S(t_bottom), vb);
   equilibrium<S>(S(1.0), S(0.0), S(0.0), S(t_top), vt);
@@ -369,24 +392,10 @@ void boundary(int lx, int ly, double t_bottom, double t_top, S* ft) {
   for (int x = 0; x < lx; ++x)
     for (int y = 0; y < ly; ++y) {
       if (y >= 3 && y < ly - 3) continue;
-      const S* v = (y < 3) ? vb : vt;
-      bool unknown[Q];
-      bool any = false;
-      for (int l = 0; l < Q; ++l) {
-        const int ys = y - M.cy[l];
-        unknown[l] = (ys < 0 || ys >= ly);
-        any = any || unknown[l];
-      }
-      if (!any) continue;
-      S num(0.0), den(0.0);
-      for (int l = 0; l < Q; ++l)
-        if (!unknown[l]) {
-          num += ft[idx(l, x, y, lx, ly)];
-          den += v[l];
-        }
-      const S rho_w = num / den;
-      for (int l = 0; l < Q; ++l)
-        if (unknown[l]) ft[idx(l, x, y, lx, ly)] = rho_w * v[l];
+      S site[Q];
+      for (int l = 0; l < Q; ++l) site[l] = ft[idx(l, x, y, lx, ly)];
+      boundary_site<S>(y, ly, vb, vt, site);
+      for (int l = 0; l < Q; ++l) ft[idx(l, x, y, lx, ly)] = site[l];
     }
 }
 
@@ -566,6 +575,30 @@ void oracle_moments(int lx, int ly, const double* f, double* rho, double* ux,
       const long s = (long)x * ly + y;
       macroscopic<double>(in, rho[s], ux[s], uy[s], T[s]);
     }
+}
+
+// One full step evaluated at n chosen sites only: out[i*37 + l] is the
+// post-collision population l at (xs[i], ys[i]) after propagate, bc and
+// collide applied to the state f (for spot checks of large lattices).
+void oracle_step_sites(int lx, int ly, const Params* P, const double* f, int n,
+                       const int32_t* xs, const int32_t* ys, double* out) {
+  const Model& M = model();
+  double vb[Q], vt[Q];
+  equilibrium<double>(1.0, 0.0, 0.0, P->t_bottom, vb);
+  equilibrium<double>(1.0, 0.0, 0.0, P->t_top, vt);
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < n; ++i) {
+    const int x = xs[i], y = ys[i];
+    double ft[Q];
+    for (int l = 0; l < Q; ++l) {
+      const int xs_ = wrap(x - M.cx[l], lx);
+      int ys_ = y - M.cy[l];
+      if (P->ybc == 1) ys_ = wrap(ys_, ly);
+      ft[l] = (ys_ < 0 || ys_ >= ly) ? std::nan("") : f[idx(l, xs_, ys_, lx, ly)];
+    }
+    if (P->ybc == 0) boundary_site<double>(y, ly, vb, vt, ft);
+    collide_site<double>(*P, ft, out + (size_t)i * Q);
+  }
 }
 
 double oracle_kinetic_energy(int lx, int ly, const double* f) {

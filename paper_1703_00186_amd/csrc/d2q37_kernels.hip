@@ -1,0 +1,736 @@
+// D2Q37 kernels for gfx950 (MI355X) and their host launchers.
+//
+// Site kernels map one thread to one lattice site.  A workgroup is a tile of
+// BY consecutive rows (y, the contiguous direction) by BX columns, BY*BX = 256
+// (four wave64s).  Tiles are numbered column-major (all row tiles of a column
+// first), and the flat workgroup index is remapped so that consecutive tiles
+// land on the same XCD: workgroups are handed to the 8 XCDs round-robin, and
+// a population's misaligned row segment shares its end cache lines with the
+// neighbouring row tile of the same column, which then hits that XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include "d2q37_launch.h"
+
+namespace d2q37 {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kXcds = 8;
+
+struct Tiling {
+  int by, bx;    // tile shape (rows, columns)
+  int nty, ntx;  // tiles along y and x
+  unsigned nb;   // total tiles
+};
+
+Tiling make_tiling(int lx, int ly) {
+  Tiling t;
+  t.by = ly > 128 ? 256 : (ly > 64 ? 128 : 64);
+  t.bx = kThreads / t.by;
+  t.nty = (ly + t.by - 1) / t.by;
+  t.ntx = (lx + t.bx - 1) / t.bx;
+  t.nb = unsigned(t.nty) * unsigned(t.ntx);
+  return t;
+}
+
+// Tile of this workgroup after the XCD-aware remap (a bijection of [0, nb)).
+__device__ __forceinline__ unsigned tile_index(unsigned nb) {
+  const unsigned b = blockIdx.x;
+  const unsigned q = nb / kXcds, rem = nb % kXcds;
+  const unsigned xcd = b % kXcds, j = b / kXcds;
+  return xcd * q + (xcd < rem ? xcd : rem) + j;
+}
+
+// Physical (x, y) of this thread; false if it falls outside the lattice.
+__device__ __forceinline__ bool site_of(const Geom& g, int by, int bx, int nty, unsigned nb,
+                                        int& x, int& y) {
+  const unsigned t = tile_index(nb);
+  const int ty = int(t % unsigned(nty)), tx = int(t / unsigned(nty));
+  const int lin = threadIdx.x;
+  y = ty * by + (lin % by);
+  x = tx * bx + (lin / by);
+  return x < g.lx && y < g.ly;
+}
+
+template <class S>
+__device__ __forceinline__ long long padded(const Geom& g, int X, int Y) {
+  return (long long)X * g.cs + Y;
+}
+
+// Gather of propagate: f_l = src(l, x - e_lx, y - e_ly) (Eq. (1), Fig. 4).
+template <class S, class A>
+__device__ __forceinline__ void gather(const S* __restrict__ src, const Geom& g, long long site,
+                                       A (&f)[Q]) {
+#pragma unroll
+  for (int l = 0; l < Q; ++l) f[l] = A(src[l * g.ps + site - EX[l] * g.cs - EY[l]]);
+}
+
+template <class S, class A>
+__device__ __forceinline__ void load_site(const S* __restrict__ src, const Geom& g,
+                                          long long site, A (&f)[Q]) {
+#pragma unroll
+  for (int l = 0; l < Q; ++l) f[l] = A(src[l * g.ps + site]);
+}
+
+template <class S, class A>
+__device__ __forceinline__ void store_site(S* __restrict__ dst, const Geom& g, long long site,
+                                           const A (&f)[Q]) {
+#pragma unroll
+  for (int l = 0; l < Q; ++l) dst[l * g.ps + site] = S(f[l]);
+}
+
+__device__ __forceinline__ bool on_wall_rows(const Geom& g, int y) {
+  return g.walls && (y < 3 || y >= g.ly - 3);
+}
+
+// ---------------------------------------------------------------------------
+// Fused step: propagate (gather), bc on wall rows, collide, store; the three
+// edge columns are also written into the opposite halo so the next step needs
+// no separate halo refresh.
+// ---------------------------------------------------------------------------
+template <class S, class A, bool kReg, bool kTape>
+__global__ __launch_bounds__(kThreads) void k_fused(const S* __restrict__ src,
+                                                    S* __restrict__ dst, Geom g, Phys P,
+                                                    double* __restrict__ tape, int by, int bx,
+                                                    int nty, unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const long long site = padded<S>(g, x + HX, y + g.hy);
+  A f[Q];
+  gather<S, A>(src, g, site, f);
+  if (on_wall_rows(g, y)) wall_site<A>(f, y, g.ly, P.th_bottom, P.th_top, P.rho_ref);
+  const Tape4 m = collide_site<A, kReg>(f, P);
+  if (kTape) {
+    const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
+    tape[s] = m.rho;
+    tape[S2 + s] = m.jx;
+    tape[2 * S2 + s] = m.jy;
+    tape[3 * S2 + s] = m.e;
+  }
+  store_site<S, A>(dst, g, site, f);
+  if (x < HX) store_site<S, A>(dst, g, site + (long long)g.lx * g.cs, f);
+  if (x >= g.lx - HX) store_site<S, A>(dst, g, site - (long long)g.lx * g.cs, f);
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_propagate(const S* __restrict__ src,
+                                                        S* __restrict__ dst, Geom g, int by,
+                                                        int bx, int nty, unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const long long site = padded<S>(g, x + HX, y + g.hy);
+#pragma unroll
+  for (int l = 0; l < Q; ++l) dst[l * g.ps + site] = src[l * g.ps + site - EX[l] * g.cs - EY[l]];
+}
+
+template <class S, class A, bool kReg>
+__global__ __launch_bounds__(kThreads) void k_collide(const S* __restrict__ src,
+                                                      S* __restrict__ dst, Geom g, Phys P,
+                                                      int by, int bx, int nty, unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const long long site = padded<S>(g, x + HX, y + g.hy);
+  A f[Q];
+  load_site<S, A>(src, g, site, f);
+  collide_site<A, kReg>(f, P);
+  store_site<S, A>(dst, g, site, f);
+}
+
+// bc on the six wall rows, in place; one thread per (x, wall row).
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_bc(S* __restrict__ buf, Geom g, Phys P) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= g.lx * 6) return;
+  const int x = i / 6, r = i % 6;
+  const int y = r < 3 ? r : g.ly - 6 + r;
+  const long long site = padded<S>(g, x + HX, y + g.hy);
+  double f[Q];
+  load_site<S, double>(buf, g, site, f);
+  wall_site<double>(f, y, g.ly, P.th_bottom, P.th_top, P.rho_ref);
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    const int ys = y - EY[l];
+    if (ys < 0 || ys >= g.ly) buf[l * g.ps + site] = S(f[l]);
+  }
+}
+
+// Halo columns: X in [0, 3) <- X + lx, X in [lx + 3, lx + 6) <- X - lx, all rows.
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_halo_x(S* __restrict__ buf, Geom g) {
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long per_l = 6LL * g.ny;
+  if (i >= per_l * Q) return;
+  const int l = int(i / per_l);
+  const int c = int((i % per_l) / g.ny), Y = int(i % g.ny);
+  const int Xd = c < 3 ? c : g.lx + c;
+  const int Xs = c < 3 ? g.lx + c : c;
+  buf[l * g.ps + (long long)Xd * g.cs + Y] = buf[l * g.ps + (long long)Xs * g.cs + Y];
+}
+
+// Halo rows (periodic y only): three rows below and above, all padded columns.
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_halo_y(S* __restrict__ buf, Geom g) {
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long per_l = 6LL * g.nx;
+  if (i >= per_l * Q) return;
+  const int l = int(i / per_l);
+  const int X = int((i % per_l) / 6), r = int(i % 6);
+  const int Yd = r < 3 ? g.hy - 3 + r : g.hy + g.ly + (r - 3);
+  const int Ys = r < 3 ? g.hy + g.ly - 3 + r : g.hy + (r - 3);
+  const long long col = l * g.ps + (long long)X * g.cs;
+  buf[col + Yd] = buf[col + Ys];
+}
+
+// f = f^eq(rho0, u0, T0) - w rho_ref, reconstructed from the Hermite
+// coefficients of the Gaussian (no forcing shift at t = 0).
+template <class S, class A>
+__global__ __launch_bounds__(kThreads) void k_init_feq(S* __restrict__ dst,
+                                                       const double* __restrict__ rho,
+                                                       const double* __restrict__ ux,
+                                                       const double* __restrict__ uy,
+                                                       const double* __restrict__ T, Geom g,
+                                                       Phys P, int by, int bx, int nty,
+                                                       unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const long long s = (long long)x * g.ly + y;
+  double aeq[5][5];
+  equilibrium_coeffs(rho[s], ux[s], uy[s], T[s] - 1.0, aeq);
+  aeq[0][0] = rho[s] - P.rho_ref;
+  A b[5][5];
+#pragma unroll
+  for (int p = 0; p < 5; ++p)
+#pragma unroll
+    for (int q = 0; q + p < 5; ++q) b[p][q] = A(aeq[p][q]);
+  A f[Q];
+  reconstruct<A>(b, f);
+  store_site<S, A>(dst, g, padded<S>(g, x + HX, y + g.hy), f);
+}
+
+// Eq. (2) in FP64 from the stored (possibly shifted FP32) populations.
+template <class S>
+__device__ __forceinline__ Macro site_macro(const S* __restrict__ src, const Geom& g,
+                                            long long site, double rho_ref) {
+  double f[Q];
+  load_site<S, double>(src, g, site, f);
+  double a[5][5];
+  project<double>(f, a);
+  return macro_from(rho_ref + a[0][0], a[1][0], a[0][1], a[2][0], a[0][2]);
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_moments(const S* __restrict__ src,
+                                                      double* __restrict__ rho,
+                                                      double* __restrict__ ux,
+                                                      double* __restrict__ uy,
+                                                      double* __restrict__ T, Geom g, Phys P,
+                                                      int by, int bx, int nty, unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const Macro m = site_macro<S>(src, g, padded<S>(g, x + HX, y + g.hy), P.rho_ref);
+  const long long s = (long long)x * g.ly + y;
+  if (rho) rho[s] = m.rho;
+  if (ux) ux[s] = m.ux;
+  if (uy) uy[s] = m.uy;
+  if (T) T[s] = 1.0 + m.th;
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_check(const S* __restrict__ src,
+                                                    unsigned int* __restrict__ flag, Geom g,
+                                                    Phys P, int by, int bx, int nty,
+                                                    unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const long long site = padded<S>(g, x + HX, y + g.hy);
+  bool bad = false;
+#pragma unroll
+  for (int l = 0; l < Q; ++l) bad |= !isfinite(double(src[l * g.ps + site]));
+  const Macro m = site_macro<S>(src, g, site, P.rho_ref);
+  bad |= !(m.rho > 0.0) || !(1.0 + m.th > 0.0);
+  if (bad) atomicAdd(flag, 1u);
+}
+
+// compact [37][lx][ly] <-> padded
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_pack(const S* __restrict__ padded_buf,
+                                                   S* __restrict__ compact, Geom g) {
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long S2 = (long long)g.lx * g.ly;
+  if (i >= S2 * Q) return;
+  const int l = int(i / S2);
+  const int x = int((i % S2) / g.ly), y = int(i % g.ly);
+  compact[i] = padded_buf[l * g.ps + (long long)(x + HX) * g.cs + (y + g.hy)];
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_unpack(const S* __restrict__ compact,
+                                                     S* __restrict__ padded_buf, Geom g) {
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long S2 = (long long)g.lx * g.ly;
+  if (i >= S2 * Q) return;
+  const int l = int(i / S2);
+  const int x = int((i % S2) / g.ly), y = int(i % g.ly);
+  padded_buf[l * g.ps + (long long)(x + HX) * g.cs + (y + g.hy)] = compact[i];
+}
+
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_populations_f64(const S* __restrict__ padded_buf,
+                                                              double* __restrict__ out, Geom g,
+                                                              double rho_ref) {
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long S2 = (long long)g.lx * g.ly;
+  if (i >= S2 * Q) return;
+  const int l = int(i / S2);
+  const int x = int((i % S2) / g.ly), y = int(i % g.ly);
+  double w = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (k == l) w = W[k];
+  out[i] = double(padded_buf[l * g.ps + (long long)(x + HX) * g.cs + (y + g.hy)]) + rho_ref * w;
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero(unsigned int* __restrict__ p, long long n) {
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint.
+// ---------------------------------------------------------------------------
+
+// Block-wide sum of one double per thread; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kThreads];
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// KE = (1/2) sum rho |u|^2; dKE/df_l = c_l . u - |u|^2 / 2.
+__global__ __launch_bounds__(kThreads) void k_loss_ke(const double* __restrict__ src,
+                                                      double* __restrict__ lambda,
+                                                      double* __restrict__ partials, Geom g,
+                                                      int by, int bx, int nty, unsigned nb) {
+  int x, y;
+  const bool in = site_of(g, by, bx, nty, nb, x, y);
+  double ke = 0.0;
+  if (in) {
+    const Macro m = site_macro<double>(src, g, padded<double>(g, x + HX, y + g.hy), 0.0);
+    const double u2 = m.ux * m.ux + m.uy * m.uy;
+    ke = 0.5 * m.rho * u2;
+    if (lambda) {
+      const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
+#pragma unroll
+      for (int l = 0; l < Q; ++l)
+        lambda[l * S2 + s] = R * (EX[l] * m.ux + EY[l] * m.uy) - 0.5 * u2;
+    }
+  }
+  const double tot = block_sum(ke);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sum(const double* __restrict__ partials, int n,
+                                                  double* __restrict__ out) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) v += partials[i];
+  const double tot = block_sum(v);
+  if (threadIdx.x == 0) *out = tot;
+}
+
+// Gradient of a^eq_pq = rho h_p(Ux) h_q(Uy) contracted with L_pq:
+// returns (dRho, dUx, dUy, dTh).
+struct EqGrad {
+  double rho, ux, uy, th;
+};
+
+__device__ __forceinline__ EqGrad equilibrium_grad(const double (&L)[5][5], double rho,
+                                                   double Ux, double Uy, double th) {
+  double hx[5], hy[5], dxU[5], dxT[5], dyU[5], dyT[5];
+  gauss_hermite(Ux, th, hx);
+  gauss_hermite(Uy, th, hy);
+  gauss_hermite_d(Ux, th, dxU, dxT);
+  gauss_hermite_d(Uy, th, dyU, dyT);
+  EqGrad e{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int p = 0; p < 5; ++p)
+#pragma unroll
+    for (int q = 0; q + p < 5; ++q) {
+      e.rho += L[p][q] * hx[p] * hy[q];
+      e.ux += L[p][q] * dxU[p] * hy[q];
+      e.uy += L[p][q] * hx[p] * dyU[q];
+      e.th += L[p][q] * (dxT[p] * hy[q] + hx[p] * dyT[q]);
+    }
+  e.ux *= rho;
+  e.uy *= rho;
+  e.th *= rho;
+  return e;
+}
+
+// L_pq = sum_l lambda_l w_l H_pq(c_l) / (p! q!)
+__device__ __forceinline__ void adjoint_project(const double (&lam)[Q], double (&L)[5][5]) {
+  double lw[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) lw[l] = lam[l] * W[l];
+  project<double>(lw, L);
+#pragma unroll
+  for (int p = 0; p < 5; ++p)
+#pragma unroll
+    for (int q = 0; q + p < 5; ++q) L[p][q] *= INVFAC[p] * INVFAC[q];
+}
+
+// lambda_out = P^T B^T C^T lambda_in for one step (scatter form).
+template <bool kReg>
+__global__ __launch_bounds__(kThreads) void k_adjoint(const double* __restrict__ tape,
+                                                      const double* __restrict__ lam_in,
+                                                      double* __restrict__ lam_out, Geom g,
+                                                      Phys P, int by, int bx, int nty,
+                                                      unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
+  double lam[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) lam[l] = lam_in[l * S2 + s];
+  const double rho = tape[s], jx = tape[S2 + s], jy = tape[2 * S2 + s], e = tape[3 * S2 + s];
+  const double inv = 1.0 / rho;
+  const double ux = jx * inv, uy = jy * inv;
+  const double u2 = ux * ux + uy * uy;
+  const double th = 0.5 * e * inv - 1.0 - 0.5 * u2;
+  // C^T: the collision as a function of the pre-collision populations.
+  double L[5][5];
+  adjoint_project(lam, L);
+  double Lw[5][5];
+#pragma unroll
+  for (int p = 0; p < 5; ++p)
+#pragma unroll
+    for (int q = 0; q + p < 5; ++q) Lw[p][q] = P.omega * L[p][q];
+  const EqGrad G =
+      equilibrium_grad(Lw, rho, ux + P.tau_gx, uy + P.tau_gy, th + P.dtheta);
+  const double g00 = G.rho - (ux * G.ux + uy * G.uy) * inv + G.th * (0.5 * u2 - th) * inv;
+  const double g10 = (G.ux - ux * G.th) * inv;
+  const double g01 = (G.uy - uy * G.th) * inv;
+  const double ge2 = 0.5 * G.th * inv;
+  double B[5][5];
+  const double keep = 1.0 - P.omega;
+#pragma unroll
+  for (int p = 0; p < 5; ++p)
+#pragma unroll
+    for (int q = 0; q + p < 5; ++q) B[p][q] = kReg ? keep * L[p][q] : 0.0;
+  B[0][0] += g00;
+  B[1][0] += g10;
+  B[0][1] += g01;
+  B[2][0] += ge2;
+  B[0][2] += ge2;
+  double mu[Q];
+  expand<double>(B, mu);
+  if (!kReg) {
+#pragma unroll
+    for (int l = 0; l < Q; ++l) mu[l] += keep * lam[l];
+  }
+  // B^T: on wall rows the unknown populations were rho_w v_l with
+  // rho_w = sum_K f / sum_K v.
+  if (on_wall_rows(g, y)) {
+    const double thw = y < 3 ? P.th_bottom : P.th_top;
+    double vk = 0.0, su = 0.0;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      const int ys = y - EY[l];
+      const bool unknown = ys < 0 || ys >= g.ly;
+      const double v = wall_feq(l, thw);
+      if (unknown)
+        su += mu[l] * v;
+      else
+        vk += v;
+    }
+    const double add = su / vk;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      const int ys = y - EY[l];
+      const bool unknown = ys < 0 || ys >= g.ly;
+      mu[l] = unknown ? 0.0 : mu[l] + add;
+    }
+  }
+  // P^T: the population that arrived here came from (x - e_lx, y - e_ly).
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    const int ys = y - EY[l];
+    if (g.walls && (ys < 0 || ys >= g.ly)) continue;
+    int xs = x - EX[l];
+    xs += xs < 0 ? g.lx : (xs >= g.lx ? -g.lx : 0);
+    int yd = ys;
+    if (!g.walls) yd += yd < 0 ? g.ly : (yd >= g.ly ? -g.ly : 0);
+    lam_out[l * S2 + (long long)xs * g.ly + yd] = mu[l];
+  }
+  // Populations leaving through a wall from this site reach no site: zero.
+  if (on_wall_rows(g, y)) {
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      const int yd = y + EY[l];
+      if (yd < 0 || yd >= g.ly) lam_out[l * S2 + s] = 0.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_init_adjoint(
+    const double* __restrict__ lam0, const double* __restrict__ rho,
+    const double* __restrict__ ux, const double* __restrict__ uy, const double* __restrict__ T,
+    double* __restrict__ drho, double* __restrict__ dux, double* __restrict__ duy,
+    double* __restrict__ dT, Geom g, int by, int bx, int nty, unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
+  double lam[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) lam[l] = lam0[l * S2 + s];
+  double L[5][5];
+  adjoint_project(lam, L);
+  const EqGrad G = equilibrium_grad(L, rho[s], ux[s], uy[s], T[s] - 1.0);
+  if (drho) drho[s] = G.rho;
+  if (dux) dux[s] = G.ux;
+  if (duy) duy[s] = G.uy;
+  if (dT) dT[s] = G.th;
+}
+
+unsigned grid_1d(long long n) { return unsigned((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const long long n = (long long)(bytes / 4);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(grid_1d(n)), dim3(kThreads), 0, s,
+                     static_cast<unsigned int*>(p), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_halo(void* buf, const Geom& g, int prec, hipStream_t s) {
+  const long long nx_el = 6LL * g.ny * Q, ny_el = 6LL * g.nx * Q;
+  if (prec == kF64) {
+    hipLaunchKernelGGL(k_halo_x<double>, dim3(grid_1d(nx_el)), dim3(kThreads), 0, s,
+                       static_cast<double*>(buf), g);
+    if (!g.walls)
+      hipLaunchKernelGGL(k_halo_y<double>, dim3(grid_1d(ny_el)), dim3(kThreads), 0, s,
+                         static_cast<double*>(buf), g);
+  } else {
+    hipLaunchKernelGGL(k_halo_x<float>, dim3(grid_1d(nx_el)), dim3(kThreads), 0, s,
+                       static_cast<float*>(buf), g);
+    if (!g.walls)
+      hipLaunchKernelGGL(k_halo_y<float>, dim3(grid_1d(ny_el)), dim3(kThreads), 0, s,
+                         static_cast<float*>(buf), g);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(const void* src, void* dst, const Geom& g, const Phys& p, int prec,
+                        int regularize, double* tape, hipStream_t s) {
+  const Tiling t = make_tiling(g.lx, g.ly);
+  const dim3 grid(t.nb), block(kThreads);
+  if (prec == kF64) {
+    const double* a = static_cast<const double*>(src);
+    double* b = static_cast<double*>(dst);
+    if (regularize) {
+      if (tape)
+        hipLaunchKernelGGL((k_fused<double, double, true, true>), grid, block, 0, s, a, b, g, p,
+                           tape, t.by, t.bx, t.nty, t.nb);
+      else
+        hipLaunchKernelGGL((k_fused<double, double, true, false>), grid, block, 0, s, a, b, g,
+                           p, tape, t.by, t.bx, t.nty, t.nb);
+    } else {
+      if (tape)
+        hipLaunchKernelGGL((k_fused<double, double, false, true>), grid, block, 0, s, a, b, g,
+                           p, tape, t.by, t.bx, t.nty, t.nb);
+      else
+        hipLaunchKernelGGL((k_fused<double, double, false, false>), grid, block, 0, s, a, b, g,
+                           p, tape, t.by, t.bx, t.nty, t.nb);
+    }
+  } else {
+    if (tape) return hipErrorInvalidValue;
+    const float* a = static_cast<const float*>(src);
+    float* b = static_cast<float*>(dst);
+    if (regularize)
+      hipLaunchKernelGGL((k_fused<float, float, true, false>), grid, block, 0, s, a, b, g, p,
+                         nullptr, t.by, t.bx, t.nty, t.nb);
+    else
+      hipLaunchKernelGGL((k_fused<float, float, false, false>), grid, block, 0, s, a, b, g, p,
+                         nullptr, t.by, t.bx, t.nty, t.nb);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_propagate(const void* src, void* dst, const Geom& g, int prec,
+                            hipStream_t s) {
+  const Tiling t = make_tiling(g.lx, g.ly);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_propagate<double>, dim3(t.nb), dim3(kThreads), 0, s,
+                       static_cast<const double*>(src), static_cast<double*>(dst), g, t.by,
+                       t.bx, t.nty, t.nb);
+  else
+    hipLaunchKernelGGL(k_propagate<float>, dim3(t.nb), dim3(kThreads), 0, s,
+                       static_cast<const float*>(src), static_cast<float*>(dst), g, t.by, t.bx,
+                       t.nty, t.nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_bc(void* buf, const Geom& g, const Phys& p, int prec, hipStream_t s) {
+  if (!g.walls) return hipSuccess;
+  const unsigned grid = grid_1d(6LL * g.lx);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_bc<double>, dim3(grid), dim3(kThreads), 0, s,
+                       static_cast<double*>(buf), g, p);
+  else
+    hipLaunchKernelGGL(k_bc<float>, dim3(grid), dim3(kThreads), 0, s, static_cast<float*>(buf),
+                       g, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_collide(const void* src, void* dst, const Geom& g, const Phys& p, int prec,
+                          int regularize, hipStream_t s) {
+  const Tiling t = make_tiling(g.lx, g.ly);
+  const dim3 grid(t.nb), block(kThreads);
+  if (prec == kF64) {
+    const double* a = static_cast<const double*>(src);
+    double* b = static_cast<double*>(dst);
+    if (regularize)
+      hipLaunchKernelGGL((k_collide<double, double, true>), grid, block, 0, s, a, b, g, p, t.by,
+                         t.bx, t.nty, t.nb);
+    else
+      hipLaunchKernelGGL((k_collide<double, double, false>), grid, block, 0, s, a, b, g, p,
+                         t.by, t.bx, t.nty, t.nb);
+  } else {
+    const float* a = static_cast<const float*>(src);
+    float* b = static_cast<float*>(dst);
+    if (regularize)
+      hipLaunchKernelGGL((k_collide<float, float, true>), grid, block, 0, s, a, b, g, p, t.by,
+                         t.bx, t.nty, t.nb);
+    else
+      hipLaunchKernelGGL((k_collide<float, float, false>), grid, block, 0, s, a, b, g, p, t.by,
+                         t.bx, t.nty, t.nb);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init_feq(void* dst, const double* rho, const double* ux, const double* uy,
+                           const double* T, const Geom& g, const Phys& p, int prec,
+                           hipStream_t s) {
+  const Tiling t = make_tiling(g.lx, g.ly);
+  if (prec == kF64)
+    hipLaunchKernelGGL((k_init_feq<double, double>), dim3(t.nb), dim3(kThreads), 0, s,
+                       static_cast<double*>(dst), rho, ux, uy, T, g, p, t.by, t.bx, t.nty,
+                       t.nb);
+  else
+    hipLaunchKernelGGL((k_init_feq<float, float>), dim3(t.nb), dim3(kThreads), 0, s,
+                       static_cast<float*>(dst), rho, ux, uy, T, g, p, t.by, t.bx, t.nty, t.nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const void* src, double* rho, double* ux, double* uy, double* T,
+                          const Geom& g, const Phys& p, int prec, hipStream_t s) {
+  const Tiling t = make_tiling(g.lx, g.ly);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_moments<double>, dim3(t.nb), dim3(kThreads), 0, s,
+                       static_cast<const double*>(src), rho, ux, uy, T, g, p, t.by, t.bx,
+                       t.nty, t.nb);
+  else
+    hipLaunchKernelGGL(k_moments<float>, dim3(t.nb), dim3(kThreads), 0, s,
+                       static_cast<const float*>(src), rho, ux, uy, T, g, p, t.by, t.bx, t.nty,
+                       t.nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const void* padded_buf, void* compact, const Geom& g, int prec,
+                       hipStream_t s) {
+  const unsigned grid = grid_1d((long long)g.lx * g.ly * Q);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_pack<double>, dim3(grid), dim3(kThreads), 0, s,
+                       static_cast<const double*>(padded_buf), static_cast<double*>(compact),
+                       g);
+  else
+    hipLaunchKernelGGL(k_pack<float>, dim3(grid), dim3(kThreads), 0, s,
+                       static_cast<const float*>(padded_buf), static_cast<float*>(compact), g);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const void* compact, void* padded_buf, const Geom& g, int prec,
+                         hipStream_t s) {
+  const unsigned grid = grid_1d((long long)g.lx * g.ly * Q);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_unpack<double>, dim3(grid), dim3(kThreads), 0, s,
+                       static_cast<const double*>(compact), static_cast<double*>(padded_buf),
+                       g);
+  else
+    hipLaunchKernelGGL(k_unpack<float>, dim3(grid), dim3(kThreads), 0, s,
+                       static_cast<const float*>(compact), static_cast<float*>(padded_buf), g);
+  return hipGetLastError();
+}
+
+hipError_t launch_populations_f64(const void* padded_buf, double* out, const Geom& g,
+                                  const Phys& p, int prec, hipStream_t s) {
+  const unsigned grid = grid_1d((long long)g.lx * g.ly * Q);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_populations_f64<double>, dim3(grid), dim3(kThreads), 0, s,
+                       static_cast<const double*>(padded_buf), out, g, 0.0);
+  else
+    hipLaunchKernelGGL(k_populations_f64<float>, dim3(grid), dim3(kThreads), 0, s,
+                       static_cast<const float*>(padded_buf), out, g, p.rho_ref);
+  return hipGetLastError();
+}
+
+hipError_t launch_check(const void* src, unsigned int* flag, const Geom& g, const Phys& p,
+                        int prec, hipStream_t s) {
+  const Tiling t = make_tiling(g.lx, g.ly);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_check<double>, dim3(t.nb), dim3(kThreads), 0, s,
+                       static_cast<const double*>(src), flag, g, p, t.by, t.bx, t.nty, t.nb);
+  else
+    hipLaunchKernelGGL(k_check<float>, dim3(t.nb), dim3(kThreads), 0, s,
+                       static_cast<const float*>(src), flag, g, p, t.by, t.bx, t.nty, t.nb);
+  return hipGetLastError();
+}
+
+int loss_ke_blocks(const Geom& g) { return int(make_tiling(g.lx, g.ly).nb); }
+
+hipError_t launch_loss_ke(const void* src, double* ke, double* lambda, double* partials,
+                          const Geom& g, hipStream_t s) {
+  const Tiling t = make_tiling(g.lx, g.ly);
+  hipLaunchKernelGGL(k_loss_ke, dim3(t.nb), dim3(kThreads), 0, s,
+                     static_cast<const double*>(src), lambda, partials, g, t.by, t.bx, t.nty,
+                     t.nb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, partials, int(t.nb), ke);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const double* tape, const double* lam_in, double* lam_out,
+                               const Geom& g, const Phys& p, int regularize, hipStream_t s) {
+  const Tiling t = make_tiling(g.lx, g.ly);
+  if (regularize)
+    hipLaunchKernelGGL(k_adjoint<true>, dim3(t.nb), dim3(kThreads), 0, s, tape, lam_in, lam_out,
+                       g, p, t.by, t.bx, t.nty, t.nb);
+  else
+    hipLaunchKernelGGL(k_adjoint<false>, dim3(t.nb), dim3(kThreads), 0, s, tape, lam_in,
+                       lam_out, g, p, t.by, t.bx, t.nty, t.nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_adjoint(const double* lam0, const double* rho, const double* ux,
+                               const double* uy, const double* T, double* drho, double* dux,
+                               double* duy, double* dT, const Geom& g, hipStream_t s) {
+  const Tiling t = make_tiling(g.lx, g.ly);
+  hipLaunchKernelGGL(k_init_adjoint, dim3(t.nb), dim3(kThreads), 0, s, lam0, rho, ux, uy, T,
+                     drho, dux, duy, dT, g, t.by, t.bx, t.nty, t.nb);
+  return hipGetLastError();
+}
+
+}  // namespace d2q37

@@ -1,0 +1,280 @@
+"""Python binding of the D2Q37 C ABI (include/lb.h).
+
+Argument marshalling only: every step of the lattice Boltzmann path runs in
+the gfx950 kernels of libd2q37_lb.so.  PyTorch supplies device memory (the
+workspace and all field / population tensors) and the stream.  There is no
+CPU fallback: if the library is missing, loading fails with an error.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from . import build as _build
+
+Q = 37
+
+LB_FP64, LB_FP32_SHIFTED = 0, 1
+LB_Y_WALLS, LB_Y_PERIODIC = 0, 1
+LB_LAYOUT_SOA, LB_LAYOUT_COLUMN = 0, 1
+LB_KERNEL_FUSED, LB_KERNEL_SPLIT = 0, 1
+
+ERRORS = {-1: "LB_E_ARG", -2: "LB_E_WORKSPACE", -3: "LB_E_HIP", -4: "LB_E_STATE",
+          -5: "LB_E_NONFINITE"}
+
+EXPORTS = [
+    "lb_last_error", "lb_version", "lb_workspace_bytes", "lb_init", "lb_free", "lb_set_stream",
+    "lb_set_params", "lb_step", "lb_moments", "lb_get_state", "lb_set_state",
+    "lb_get_populations", "lb_halo", "lb_propagate", "lb_bc", "lb_collide", "lb_get_scratch",
+    "lb_set_scratch", "lb_step_record", "lb_loss_ke", "lb_adjoint_step", "lb_init_adjoint",
+]
+
+
+class LBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("ybc", ctypes.c_int32), ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+                ("t_bottom", ctypes.c_double), ("t_top", ctypes.c_double),
+                ("rho_ref", ctypes.c_double), ("regularize", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("check_finite", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def load_library():
+    """Loads libd2q37_lb.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError("libd2q37_lb.so is not built; run `python -m paper_1703_00186_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    Lp, Pp = ctypes.POINTER(Lattice), ctypes.POINTER(Params)
+    sig = {
+        "lb_last_error": ([], ctypes.c_char_p),
+        "lb_version": ([], i),
+        "lb_workspace_bytes": ([Lp, Pp, ctypes.POINTER(sz)], i),
+        "lb_init": ([Lp, Pp, vp, sz, vp, vp, vp, vp, vp, ctypes.POINTER(vp)], i),
+        "lb_free": ([vp], i),
+        "lb_set_stream": ([vp, vp], i),
+        "lb_set_params": ([vp, Pp], i),
+        "lb_step": ([vp, i], i),
+        "lb_moments": ([vp, vp, vp, vp, vp], i),
+        "lb_get_state": ([vp, vp], i),
+        "lb_set_state": ([vp, vp], i),
+        "lb_get_populations": ([vp, vp], i),
+        "lb_halo": ([vp], i),
+        "lb_propagate": ([vp], i),
+        "lb_bc": ([vp], i),
+        "lb_collide": ([vp], i),
+        "lb_get_scratch": ([vp, vp], i),
+        "lb_set_scratch": ([vp, vp], i),
+        "lb_step_record": ([vp, i, vp], i),
+        "lb_loss_ke": ([vp, vp, vp], i),
+        "lb_adjoint_step": ([vp, vp, vp, vp], i),
+        "lb_init_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LBError(rc, load_library().lb_last_error().decode())
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(tau=0.7, g=(0.0, -1e-4), t_bottom=1.5, t_top=0.5, rho_ref=1.0, regularize=1,
+                kernel="fused", check_finite=0) -> Params:
+    k = {"fused": LB_KERNEL_FUSED, "split": LB_KERNEL_SPLIT}[kernel]
+    return Params(float(tau), float(g[0]), float(g[1]), float(t_bottom), float(t_top),
+                  float(rho_ref), int(regularize), k, int(check_finite), 0)
+
+
+def make_lattice(lx, ly, precision="fp64", ybc="walls", layout="soa") -> Lattice:
+    p = {"fp64": LB_FP64, "fp32s": LB_FP32_SHIFTED}[precision]
+    y = {"walls": LB_Y_WALLS, "periodic": LB_Y_PERIODIC}[ybc]
+    lay = {"soa": LB_LAYOUT_SOA, "column": LB_LAYOUT_COLUMN}[layout]
+    return Lattice(int(lx), int(ly), p, y, lay, 0)
+
+
+class LB:
+    """One D2Q37 lattice on one GPU.
+
+    Initial fields rho0, ux0, uy0, T0 are [lx, ly] float64 (numpy or torch);
+    they are copied to the device and the state starts at f^eq(rho0, u0, T0).
+    """
+
+    def __init__(self, lx, ly, rho0, ux0, uy0, T0, *, precision="fp64", ybc="walls",
+                 layout="soa", device="cuda:0", **params):
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.lx, self.ly = int(lx), int(ly)
+        self.precision = precision
+        self.lat = make_lattice(lx, ly, precision, ybc, layout)
+        self.par = make_params(**params)
+        nbytes = ctypes.c_size_t(0)
+        _check(self.lib.lb_workspace_bytes(ctypes.byref(self.lat), ctypes.byref(self.par),
+                                           ctypes.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        fields = [self.field(a) for a in (rho0, ux0, uy0, T0)]
+        self.ctx = ctypes.c_void_p(0)
+        with torch.cuda.device(self.device):
+            _check(self.lib.lb_init(ctypes.byref(self.lat), ctypes.byref(self.par),
+                                    _ptr(self.workspace), nbytes.value, self._stream(),
+                                    *[_ptr(f) for f in fields], ctypes.byref(self.ctx)))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    # -- helpers -----------------------------------------------------------
+    def _stream(self) -> ctypes.c_void_p:
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _sync_stream(self):
+        _check(self.lib.lb_set_stream(self.ctx, self._stream()))
+
+    def field(self, a) -> torch.Tensor:
+        t = torch.as_tensor(a, dtype=torch.float64)
+        if tuple(t.shape) != (self.lx, self.ly):
+            raise ValueError("field must be [lx, ly]")
+        return t.to(self.device).contiguous()
+
+    @property
+    def state_dtype(self):
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def new_populations(self, dtype=None) -> torch.Tensor:
+        return torch.empty((Q, self.lx, self.ly), dtype=dtype or self.state_dtype,
+                           device=self.device)
+
+    # -- the step ------------------------------------------------------------
+    def set_params(self, **params):
+        self.par = make_params(**params)
+        _check(self.lib.lb_set_params(self.ctx, ctypes.byref(self.par)))
+
+    def step(self, n: int = 1):
+        self._sync_stream()
+        _check(self.lib.lb_step(self.ctx, int(n)))
+
+    def moments(self):
+        self._sync_stream()
+        out = [torch.empty((self.lx, self.ly), dtype=torch.float64, device=self.device)
+               for _ in range(4)]
+        _check(self.lib.lb_moments(self.ctx, *[_ptr(t) for t in out]))
+        return tuple(out)
+
+    def get_state(self, out=None) -> torch.Tensor:
+        self._sync_stream()
+        out = self.new_populations() if out is None else out
+        _check(self.lib.lb_get_state(self.ctx, _ptr(out)))
+        return out
+
+    def set_state(self, f: torch.Tensor):
+        self._sync_stream()
+        f = f.to(self.device, self.state_dtype).contiguous()
+        _check(self.lib.lb_set_state(self.ctx, _ptr(f)))
+
+    def populations(self) -> torch.Tensor:
+        self._sync_stream()
+        out = self.new_populations(torch.float64)
+        _check(self.lib.lb_get_populations(self.ctx, _ptr(out)))
+        return out
+
+    # -- split stages ----------------------------------------------------------
+    def halo(self):
+        self._sync_stream()
+        _check(self.lib.lb_halo(self.ctx))
+
+    def propagate(self):
+        self._sync_stream()
+        _check(self.lib.lb_propagate(self.ctx))
+
+    def bc(self):
+        self._sync_stream()
+        _check(self.lib.lb_bc(self.ctx))
+
+    def collide(self):
+        self._sync_stream()
+        _check(self.lib.lb_collide(self.ctx))
+
+    def get_scratch(self) -> torch.Tensor:
+        self._sync_stream()
+        out = self.new_populations()
+        _check(self.lib.lb_get_scratch(self.ctx, _ptr(out)))
+        return out
+
+    def set_scratch(self, f: torch.Tensor):
+        self._sync_stream()
+        f = f.to(self.device, self.state_dtype).contiguous()
+        _check(self.lib.lb_set_scratch(self.ctx, _ptr(f)))
+
+    # -- adjoint -------------------------------------------------------------
+    def new_tape(self, n: int) -> torch.Tensor:
+        return torch.empty((n, 4, self.lx, self.ly), dtype=torch.float64, device=self.device)
+
+    def step_record(self, n: int, tape: torch.Tensor):
+        self._sync_stream()
+        if tape.shape[0] < n or tuple(tape.shape[1:]) != (4, self.lx, self.ly):
+            raise ValueError("tape must be [>=n, 4, lx, ly]")
+        _check(self.lib.lb_step_record(self.ctx, int(n), _ptr(tape)))
+
+    def loss_ke(self, with_lambda: bool = True):
+        self._sync_stream()
+        ke = torch.empty(1, dtype=torch.float64, device=self.device)
+        lam = self.new_populations(torch.float64) if with_lambda else None
+        _check(self.lib.lb_loss_ke(self.ctx, _ptr(ke), _ptr(lam)))
+        return ke, lam
+
+    def adjoint_step(self, tape_j: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor):
+        self._sync_stream()
+        _check(self.lib.lb_adjoint_step(self.ctx, _ptr(tape_j), _ptr(lam_in), _ptr(lam_out)))
+
+    def init_adjoint(self, rho0, ux0, uy0, T0, lam0: torch.Tensor):
+        self._sync_stream()
+        fields = [self.field(a) for a in (rho0, ux0, uy0, T0)]
+        out = [torch.empty((self.lx, self.ly), dtype=torch.float64, device=self.device)
+               for _ in range(4)]
+        _check(self.lib.lb_init_adjoint(self.ctx, *[_ptr(f) for f in fields], _ptr(lam0),
+                                        *[_ptr(t) for t in out]))
+        return tuple(out)
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            self.lib.lb_free(self.ctx)
+            self.ctx = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
