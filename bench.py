@@ -37,6 +37,72 @@ def mlups(sites: int, seconds: float) -> float:
     return sites / seconds / 1e6
 
 
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_SUMMARY = os.path.join(PROFILES, "k_fused_fp64_rt1920x2048_hbm_traffic.md")
+KERNEL_SOURCES = ["paper_1703_00186_amd/csrc/d2q37_kernels.hip",
+                  "paper_1703_00186_amd/csrc/d2q37_device.h",
+                  "paper_1703_00186_amd/csrc/d2q37_constants.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(lx: int, ly: int):
+    """HBM bytes per fused launch from the committed counter summary, or None
+    when the summary is missing, is for another lattice, or the kernel
+    sources changed since the counters were taken."""
+    try:
+        vals = {}
+        for line in open(TRAFFIC_SUMMARY):
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip()
+        if vals.get("source_sha256_16") != kernel_source_hash():
+            return None
+        if vals.get("lattice") != "%dx%d" % (lx, ly):
+            return None
+        return float(vals["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 3) -> None:
+    """A plain device copy of known size (nbytes read + nbytes written per
+    launch), run so that a counter profile of this process can be scaled."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def field_errors(m, ref) -> dict:
+    """Relative errors per field of (rho, ux, uy, T): rho and T as max|d| over
+    max|ref|; u as max|du| over max(max|u|, sqrt(min T)) (the flow or thermal
+    speed, whichever is larger; rho u is a cancelling sum of thermal-speed
+    terms)."""
+    import numpy as np
+    m = [np.asarray(a, dtype=np.float64) for a in m]
+    r = [np.asarray(a, dtype=np.float64) for a in ref]
+    du = np.hypot(m[1] - r[1], m[2] - r[2])
+    scale_u = max(float(np.hypot(r[1], r[2]).max()), float(np.sqrt(r[3].min())))
+    return {"rho": float(np.abs(m[0] - r[0]).max() / np.abs(r[0]).max()),
+            "u": float(du.max() / scale_u),
+            "T": float(np.abs(m[3] - r[3]).max() / np.abs(r[3]).max())}
+
+
+def host_moments(lb, torch):
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in lb.moments()]
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -105,12 +171,14 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--lx", type=int, default=1920)
     ap.add_argument("--ly", type=int, default=2048)
-    ap.add_argument("--layout", default="soa", choices=["soa", "column"])
+    ap.add_argument("--layout", default="column", choices=["soa", "column"])
     ap.add_argument("--split-steps", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="time only the headline fused FP64 step (for profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter scale reference)")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -149,6 +217,12 @@ def main(argv=None) -> int:
                      "traffic": None, "kernel": "k_fused<double>",
                      "bytes_per_site": bytes_per_site("fp64")},
     }
+    traffic = measured_traffic(lx, ly) if args.layout == "column" else None
+    if traffic is not None:
+        out["roofline"]["traffic"] = traffic
+        out["roofline"]["traffic_unit"] = "bytes per launch"
+    if args.copy_calibration:
+        copy_calibration(torch)
     if not args.no_extras:
         lb.set_params(kernel="split")
         sp = time_split_kernels(lb, args.split_steps, torch)
@@ -159,19 +233,28 @@ def main(argv=None) -> int:
         out["split_fp64"]["collide"]["GB/s"] = round(bytes_per_site() * sites / sp["collide"] / 1e9, 1)
         out["split_fp64"]["step"] = {"ms": round(tot * 1e3, 5), "MLUPS": round(mlups(sites, tot), 1)}
         log("bench: split FP64 %s" % json.dumps(out["split_fp64"]))
+        # the split path advanced the FP64 lattice: rerun it for the comparison
+        lb.reinit(*fields)
+        lb.set_params(kernel="fused")
+        lb.step(args.warmup + args.steps)
+        m64 = host_moments(lb, torch)
         del lb
         torch.cuda.empty_cache()
-        lb32 = LB(lx, ly, *fields, precision="fp32s", layout=args.layout, kernel="fused")
-        lb32.step(args.warmup)
-        t32 = time_steps(lb32, args.steps, torch)
-        v32 = mlups(sites * args.steps, t32)
-        out["fp32_shifted"] = {
-            "MLUPS": round(v32, 2), "ms_per_step": round(t32 / args.steps * 1e3, 5),
-            "ratio_vs_fp64": round(v32 / value, 3),
-            "GB/s": round(bytes_per_site("fp32") * sites / (t32 / args.steps) / 1e9, 1)}
-        log("bench: fused FP32-shifted %.1f MLUPS (x%.2f)" % (v32, v32 / value))
-        del lb32
-        torch.cuda.empty_cache()
+        for key, prec in (("fp32_shifted", "fp32s"), ("fp32_shifted_f32sum", "fp32s_f32sum")):
+            lb32 = LB(lx, ly, *fields, precision=prec, layout=args.layout, kernel="fused")
+            lb32.step(args.warmup)
+            t32 = time_steps(lb32, args.steps, torch)
+            v32 = mlups(sites * args.steps, t32)
+            errs = field_errors(host_moments(lb32, torch), m64)
+            out[key] = {
+                "MLUPS": round(v32, 2), "ms_per_step": round(t32 / args.steps * 1e3, 5),
+                "ratio_vs_fp64": round(v32 / value, 3),
+                "GB/s": round(bytes_per_site("fp32") * sites / (t32 / args.steps) / 1e9, 1),
+                "error_vs_fp64_gpu": {k: float("%.3g" % v) for k, v in errs.items()},
+                "error_after_steps": args.warmup + args.steps}
+            log("bench: fused %s %.1f MLUPS (x%.2f), errors %s" % (prec, v32, v32 / value, errs))
+            del lb32
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle (%d steps)" % args.cpu_steps)
         out["cpu_baseline"] = cpu_baseline(lx, ly, fields, args.cpu_steps)

@@ -49,10 +49,13 @@ extern "C" {
 #define LB_E_STATE (-4)     /* call not valid in this context's state      */
 #define LB_E_NONFINITE (-5) /* check_finite found rho<=0, T<=0 or NaN/Inf  */
 
-/* lb_lattice.precision */
-#define LB_FP64 0         /* populations stored and collided in FP64              */
-#define LB_FP32_SHIFTED 1 /* FP32 storage of g_l = f_l - w_l rho_ref, FP32 sums,  */
-                          /* equilibrium coefficients and relaxation in FP64      */
+/* lb_lattice.precision.  The FP32 modes store g_l = f_l - w_l rho_ref in FP32
+ * (half the HBM traffic of FP64); moments, equilibrium coefficients,
+ * relaxation and bc are FP64 in every mode. */
+#define LB_FP64 0                /* FP64 storage, FP64 sums                     */
+#define LB_FP32_SHIFTED 1        /* FP32 storage, FP64 Hermite sums (projection */
+                                 /* and reconstruction)                         */
+#define LB_FP32_SHIFTED_F32SUM 2 /* FP32 storage, FP32 Hermite sums             */
 /* lb_lattice.ybc */
 #define LB_Y_WALLS 0    /* thermal walls below row 0 and above row ly-1 */
 #define LB_Y_PERIODIC 1 /* periodic y (no walls), for tests             */
@@ -67,7 +70,7 @@ extern "C" {
 typedef struct lb_lattice {
   int32_t lx;        /* physical sites along x (periodic), >= 6         */
   int32_t ly;        /* physical sites along y (walls), >= 6            */
-  int32_t precision; /* LB_FP64 or LB_FP32_SHIFTED                      */
+  int32_t precision; /* LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM */
   int32_t ybc;       /* LB_Y_WALLS or LB_Y_PERIODIC                     */
   int32_t layout;    /* LB_LAYOUT_SOA or LB_LAYOUT_COLUMN               */
   int32_t reserved;  /* must be 0                                       */
@@ -78,7 +81,7 @@ typedef struct lb_params {
   double gx, gy;       /* gravity (acceleration per step)                      */
   double t_bottom;     /* wall temperature below row 0                         */
   double t_top;        /* wall temperature above row ly-1                      */
-  double rho_ref;      /* shift density of LB_FP32_SHIFTED (ignored for FP64)  */
+  double rho_ref;      /* shift density of the FP32 modes (ignored for FP64)   */
   int32_t regularize;  /* 1: Hermite projection of the collision, 0: plain BGK */
   int32_t kernel;      /* LB_KERNEL_FUSED or LB_KERNEL_SPLIT                   */
   int32_t check_finite; /* 0: off; N > 0: every N steps lb_step scans the state */
@@ -128,7 +131,7 @@ int lb_step(lb_ctx* ctx, int n);
 int lb_moments(lb_ctx* ctx, double* rho, double* ux, double* uy, double* T);
 
 /* Device copies of the state in compact form [37][lx][ly]: double for
- * LB_FP64, float g_l = f_l - w_l rho_ref for LB_FP32_SHIFTED.  set_state
+ * LB_FP64, float g_l = f_l - w_l rho_ref for the FP32 modes.  set_state
  * refreshes the halos.  Used for checkpoints. */
 int lb_get_state(lb_ctx* ctx, void* f);
 int lb_set_state(lb_ctx* ctx, const void* f);

@@ -103,6 +103,12 @@ def lib():
         L.oracle_step_sites.argtypes = [i, i, pp, dp, i, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32), dp]
         L.oracle_step_sites.restype = None
+        L.oracle_run_complex.argtypes = [i, i, pp, dp, i]
+        L.oracle_run_complex.restype = None
+        L.oracle_init_feq_complex.argtypes = [i, i, dp, dp, dp, dp, dp]
+        L.oracle_init_feq_complex.restype = None
+        L.oracle_kinetic_energy_complex.argtypes = [i, i, dp, dp]
+        L.oracle_kinetic_energy_complex.restype = None
         L.oracle_ke_after_steps_complex.argtypes = [i, i, pp, dp, dp, dp, dp, i, dp]
         L.oracle_ke_after_steps_complex.restype = None
         _lib = L
@@ -240,4 +246,38 @@ def ke_after_steps_complex(params: Params, rho0, ux0, uy0, T0, nsteps: int) -> c
     dp = ctypes.POINTER(ctypes.c_double)
     lib().oracle_ke_after_steps_complex(
         lx, ly, ctypes.byref(P), *[a.ctypes.data_as(dp) for a in arrs], int(nsteps), _p(ke))
+    return complex(ke[0], ke[1])
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _cp(a: np.ndarray):
+    assert a.flags.c_contiguous and a.dtype == np.complex128
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def run_complex(f, params: Params, nsteps: int) -> np.ndarray:
+    """nsteps full steps in complex arithmetic (complex-step linearisation)."""
+    out = _c128(f).copy()
+    _, lx, ly = out.shape
+    P = params.c()
+    lib().oracle_run_complex(lx, ly, ctypes.byref(P), _cp(out), int(nsteps))
+    return out
+
+
+def init_feq_complex(rho, ux, uy, T) -> np.ndarray:
+    rho, ux, uy, T = (_c128(a) for a in (rho, ux, uy, T))
+    lx, ly = rho.shape
+    f = np.zeros((Q, lx, ly), dtype=np.complex128)
+    lib().oracle_init_feq_complex(lx, ly, _cp(rho), _cp(ux), _cp(uy), _cp(T), _cp(f))
+    return f
+
+
+def kinetic_energy_complex(f) -> complex:
+    f = _c128(f)
+    _, lx, ly = f.shape
+    ke = np.zeros(2)
+    lib().oracle_kinetic_energy_complex(lx, ly, _cp(f), _p(ke))
     return complex(ke[0], ke[1])

@@ -625,4 +625,25 @@ void oracle_ke_after_steps_complex(int lx, int ly, const Params* P,
   ke[1] = k.imag();
 }
 
+// Complex-step forms for linearisations: f_c is complex [37][lx][ly]
+// (interleaved re, im), advanced in place by nsteps full steps.
+void oracle_run_complex(int lx, int ly, const Params* P, double* f_c, int nsteps) {
+  std::vector<cplx> tmp((size_t)Q * lx * ly);
+  cplx* f = reinterpret_cast<cplx*>(f_c);
+  for (int n = 0; n < nsteps; ++n) step<cplx>(lx, ly, *P, f, tmp.data());
+}
+
+void oracle_init_feq_complex(int lx, int ly, const double* rho, const double* ux,
+                             const double* uy, const double* T, double* f_c) {
+  init_feq<cplx>(lx, ly, reinterpret_cast<const cplx*>(rho), reinterpret_cast<const cplx*>(ux),
+                 reinterpret_cast<const cplx*>(uy), reinterpret_cast<const cplx*>(T),
+                 reinterpret_cast<cplx*>(f_c));
+}
+
+void oracle_kinetic_energy_complex(int lx, int ly, const double* f_c, double* ke) {
+  const cplx k = kinetic_energy<cplx>(lx, ly, reinterpret_cast<const cplx*>(f_c));
+  ke[0] = k.real();
+  ke[1] = k.imag();
+}
+
 }  // extern "C"

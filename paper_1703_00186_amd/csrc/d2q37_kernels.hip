@@ -73,11 +73,14 @@ __device__ __forceinline__ void load_site(const S* __restrict__ src, const Geom&
   for (int l = 0; l < Q; ++l) f[l] = A(src[l * g.ps + site]);
 }
 
+// Stores of a step's output are streamed past the caches (non-temporal):
+// the next step reads them only after the whole lattice, far more than the
+// caches hold, has been written.
 template <class S, class A>
 __device__ __forceinline__ void store_site(S* __restrict__ dst, const Geom& g, long long site,
                                            const A (&f)[Q]) {
 #pragma unroll
-  for (int l = 0; l < Q; ++l) dst[l * g.ps + site] = S(f[l]);
+  for (int l = 0; l < Q; ++l) __builtin_nontemporal_store(S(f[l]), &dst[l * g.ps + site]);
 }
 
 __device__ __forceinline__ bool on_wall_rows(const Geom& g, int y) {
@@ -121,7 +124,8 @@ __global__ __launch_bounds__(kThreads) void k_propagate(const S* __restrict__ sr
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
   const long long site = padded<S>(g, x + HX, y + g.hy);
 #pragma unroll
-  for (int l = 0; l < Q; ++l) dst[l * g.ps + site] = src[l * g.ps + site - EX[l] * g.cs - EY[l]];
+  for (int l = 0; l < Q; ++l)
+    __builtin_nontemporal_store(src[l * g.ps + site - EX[l] * g.cs - EY[l]], &dst[l * g.ps + site]);
 }
 
 template <class S, class A, bool kReg>
@@ -506,6 +510,21 @@ unsigned grid_1d(long long n) { return unsigned((n + kThreads - 1) / kThreads); 
 // Launchers.
 // ---------------------------------------------------------------------------
 
+// Calls fn(S{}, A{}) with the storage type S and the arithmetic type A of a
+// precision mode: FP64 storage and sums; FP32 storage with FP64 sums; FP32
+// storage with FP32 sums.  Moments, equilibrium coefficients, relaxation and
+// bc are FP64 in every mode.
+template <class Fn>
+hipError_t by_precision(int prec, Fn fn) {
+  if (prec == kF64)
+    fn(double{}, double{});
+  else if (prec == kF32Shifted)
+    fn(float{}, double{});
+  else
+    fn(float{}, float{});
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   const long long n = (long long)(bytes / 4);
   if (n == 0) return hipSuccess;
@@ -516,186 +535,138 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 
 hipError_t launch_halo(void* buf, const Geom& g, int prec, hipStream_t s) {
   const long long nx_el = 6LL * g.ny * Q, ny_el = 6LL * g.nx * Q;
-  if (prec == kF64) {
-    hipLaunchKernelGGL(k_halo_x<double>, dim3(grid_1d(nx_el)), dim3(kThreads), 0, s,
-                       static_cast<double*>(buf), g);
+  return by_precision(prec, [&](auto sv, auto) {
+    using S = decltype(sv);
+    hipLaunchKernelGGL(k_halo_x<S>, dim3(grid_1d(nx_el)), dim3(kThreads), 0, s,
+                       static_cast<S*>(buf), g);
     if (!g.walls)
-      hipLaunchKernelGGL(k_halo_y<double>, dim3(grid_1d(ny_el)), dim3(kThreads), 0, s,
-                         static_cast<double*>(buf), g);
-  } else {
-    hipLaunchKernelGGL(k_halo_x<float>, dim3(grid_1d(nx_el)), dim3(kThreads), 0, s,
-                       static_cast<float*>(buf), g);
-    if (!g.walls)
-      hipLaunchKernelGGL(k_halo_y<float>, dim3(grid_1d(ny_el)), dim3(kThreads), 0, s,
-                         static_cast<float*>(buf), g);
-  }
-  return hipGetLastError();
+      hipLaunchKernelGGL(k_halo_y<S>, dim3(grid_1d(ny_el)), dim3(kThreads), 0, s,
+                         static_cast<S*>(buf), g);
+  });
 }
 
 hipError_t launch_fused(const void* src, void* dst, const Geom& g, const Phys& p, int prec,
                         int regularize, double* tape, hipStream_t s) {
+  if (tape && prec != kF64) return hipErrorInvalidValue;
   const Tiling t = make_tiling(g.lx, g.ly);
-  const dim3 grid(t.nb), block(kThreads);
-  if (prec == kF64) {
-    const double* a = static_cast<const double*>(src);
-    double* b = static_cast<double*>(dst);
-    if (regularize) {
-      if (tape)
-        hipLaunchKernelGGL((k_fused<double, double, true, true>), grid, block, 0, s, a, b, g, p,
-                           tape, t.by, t.bx, t.nty, t.nb);
-      else
-        hipLaunchKernelGGL((k_fused<double, double, true, false>), grid, block, 0, s, a, b, g,
-                           p, tape, t.by, t.bx, t.nty, t.nb);
-    } else {
-      if (tape)
-        hipLaunchKernelGGL((k_fused<double, double, false, true>), grid, block, 0, s, a, b, g,
-                           p, tape, t.by, t.bx, t.nty, t.nb);
-      else
-        hipLaunchKernelGGL((k_fused<double, double, false, false>), grid, block, 0, s, a, b, g,
-                           p, tape, t.by, t.bx, t.nty, t.nb);
-    }
-  } else {
-    if (tape) return hipErrorInvalidValue;
-    const float* a = static_cast<const float*>(src);
-    float* b = static_cast<float*>(dst);
-    if (regularize)
-      hipLaunchKernelGGL((k_fused<float, float, true, false>), grid, block, 0, s, a, b, g, p,
-                         nullptr, t.by, t.bx, t.nty, t.nb);
+  return by_precision(prec, [&](auto sv, auto av) {
+    using S = decltype(sv);
+    using A = decltype(av);
+    const S* a = static_cast<const S*>(src);
+    S* b = static_cast<S*>(dst);
+    const dim3 grid(t.nb), block(kThreads);
+    if (regularize && tape)
+      hipLaunchKernelGGL((k_fused<S, A, true, true>), grid, block, 0, s, a, b, g, p, tape, t.by,
+                         t.bx, t.nty, t.nb);
+    else if (regularize)
+      hipLaunchKernelGGL((k_fused<S, A, true, false>), grid, block, 0, s, a, b, g, p, tape,
+                         t.by, t.bx, t.nty, t.nb);
+    else if (tape)
+      hipLaunchKernelGGL((k_fused<S, A, false, true>), grid, block, 0, s, a, b, g, p, tape,
+                         t.by, t.bx, t.nty, t.nb);
     else
-      hipLaunchKernelGGL((k_fused<float, float, false, false>), grid, block, 0, s, a, b, g, p,
-                         nullptr, t.by, t.bx, t.nty, t.nb);
-  }
-  return hipGetLastError();
+      hipLaunchKernelGGL((k_fused<S, A, false, false>), grid, block, 0, s, a, b, g, p, tape,
+                         t.by, t.bx, t.nty, t.nb);
+  });
 }
 
 hipError_t launch_propagate(const void* src, void* dst, const Geom& g, int prec,
                             hipStream_t s) {
   const Tiling t = make_tiling(g.lx, g.ly);
-  if (prec == kF64)
-    hipLaunchKernelGGL(k_propagate<double>, dim3(t.nb), dim3(kThreads), 0, s,
-                       static_cast<const double*>(src), static_cast<double*>(dst), g, t.by,
-                       t.bx, t.nty, t.nb);
-  else
-    hipLaunchKernelGGL(k_propagate<float>, dim3(t.nb), dim3(kThreads), 0, s,
-                       static_cast<const float*>(src), static_cast<float*>(dst), g, t.by, t.bx,
-                       t.nty, t.nb);
-  return hipGetLastError();
+  return by_precision(prec, [&](auto sv, auto) {
+    using S = decltype(sv);
+    hipLaunchKernelGGL(k_propagate<S>, dim3(t.nb), dim3(kThreads), 0, s,
+                       static_cast<const S*>(src), static_cast<S*>(dst), g, t.by, t.bx, t.nty,
+                       t.nb);
+  });
 }
 
 hipError_t launch_bc(void* buf, const Geom& g, const Phys& p, int prec, hipStream_t s) {
   if (!g.walls) return hipSuccess;
   const unsigned grid = grid_1d(6LL * g.lx);
-  if (prec == kF64)
-    hipLaunchKernelGGL(k_bc<double>, dim3(grid), dim3(kThreads), 0, s,
-                       static_cast<double*>(buf), g, p);
-  else
-    hipLaunchKernelGGL(k_bc<float>, dim3(grid), dim3(kThreads), 0, s, static_cast<float*>(buf),
-                       g, p);
-  return hipGetLastError();
+  return by_precision(prec, [&](auto sv, auto) {
+    using S = decltype(sv);
+    hipLaunchKernelGGL(k_bc<S>, dim3(grid), dim3(kThreads), 0, s, static_cast<S*>(buf), g, p);
+  });
 }
 
 hipError_t launch_collide(const void* src, void* dst, const Geom& g, const Phys& p, int prec,
                           int regularize, hipStream_t s) {
   const Tiling t = make_tiling(g.lx, g.ly);
-  const dim3 grid(t.nb), block(kThreads);
-  if (prec == kF64) {
-    const double* a = static_cast<const double*>(src);
-    double* b = static_cast<double*>(dst);
+  return by_precision(prec, [&](auto sv, auto av) {
+    using S = decltype(sv);
+    using A = decltype(av);
+    const S* a = static_cast<const S*>(src);
+    S* b = static_cast<S*>(dst);
     if (regularize)
-      hipLaunchKernelGGL((k_collide<double, double, true>), grid, block, 0, s, a, b, g, p, t.by,
-                         t.bx, t.nty, t.nb);
-    else
-      hipLaunchKernelGGL((k_collide<double, double, false>), grid, block, 0, s, a, b, g, p,
+      hipLaunchKernelGGL((k_collide<S, A, true>), dim3(t.nb), dim3(kThreads), 0, s, a, b, g, p,
                          t.by, t.bx, t.nty, t.nb);
-  } else {
-    const float* a = static_cast<const float*>(src);
-    float* b = static_cast<float*>(dst);
-    if (regularize)
-      hipLaunchKernelGGL((k_collide<float, float, true>), grid, block, 0, s, a, b, g, p, t.by,
-                         t.bx, t.nty, t.nb);
     else
-      hipLaunchKernelGGL((k_collide<float, float, false>), grid, block, 0, s, a, b, g, p, t.by,
-                         t.bx, t.nty, t.nb);
-  }
-  return hipGetLastError();
+      hipLaunchKernelGGL((k_collide<S, A, false>), dim3(t.nb), dim3(kThreads), 0, s, a, b, g,
+                         p, t.by, t.bx, t.nty, t.nb);
+  });
 }
 
 hipError_t launch_init_feq(void* dst, const double* rho, const double* ux, const double* uy,
                            const double* T, const Geom& g, const Phys& p, int prec,
                            hipStream_t s) {
   const Tiling t = make_tiling(g.lx, g.ly);
-  if (prec == kF64)
-    hipLaunchKernelGGL((k_init_feq<double, double>), dim3(t.nb), dim3(kThreads), 0, s,
-                       static_cast<double*>(dst), rho, ux, uy, T, g, p, t.by, t.bx, t.nty,
-                       t.nb);
-  else
-    hipLaunchKernelGGL((k_init_feq<float, float>), dim3(t.nb), dim3(kThreads), 0, s,
-                       static_cast<float*>(dst), rho, ux, uy, T, g, p, t.by, t.bx, t.nty, t.nb);
-  return hipGetLastError();
+  return by_precision(prec, [&](auto sv, auto) {
+    using S = decltype(sv);
+    hipLaunchKernelGGL((k_init_feq<S, double>), dim3(t.nb), dim3(kThreads), 0, s,
+                       static_cast<S*>(dst), rho, ux, uy, T, g, p, t.by, t.bx, t.nty, t.nb);
+  });
 }
 
 hipError_t launch_moments(const void* src, double* rho, double* ux, double* uy, double* T,
                           const Geom& g, const Phys& p, int prec, hipStream_t s) {
   const Tiling t = make_tiling(g.lx, g.ly);
-  if (prec == kF64)
-    hipLaunchKernelGGL(k_moments<double>, dim3(t.nb), dim3(kThreads), 0, s,
-                       static_cast<const double*>(src), rho, ux, uy, T, g, p, t.by, t.bx,
-                       t.nty, t.nb);
-  else
-    hipLaunchKernelGGL(k_moments<float>, dim3(t.nb), dim3(kThreads), 0, s,
-                       static_cast<const float*>(src), rho, ux, uy, T, g, p, t.by, t.bx, t.nty,
+  return by_precision(prec, [&](auto sv, auto) {
+    using S = decltype(sv);
+    hipLaunchKernelGGL(k_moments<S>, dim3(t.nb), dim3(kThreads), 0, s,
+                       static_cast<const S*>(src), rho, ux, uy, T, g, p, t.by, t.bx, t.nty,
                        t.nb);
-  return hipGetLastError();
+  });
 }
 
 hipError_t launch_pack(const void* padded_buf, void* compact, const Geom& g, int prec,
                        hipStream_t s) {
   const unsigned grid = grid_1d((long long)g.lx * g.ly * Q);
-  if (prec == kF64)
-    hipLaunchKernelGGL(k_pack<double>, dim3(grid), dim3(kThreads), 0, s,
-                       static_cast<const double*>(padded_buf), static_cast<double*>(compact),
-                       g);
-  else
-    hipLaunchKernelGGL(k_pack<float>, dim3(grid), dim3(kThreads), 0, s,
-                       static_cast<const float*>(padded_buf), static_cast<float*>(compact), g);
-  return hipGetLastError();
+  return by_precision(prec, [&](auto sv, auto) {
+    using S = decltype(sv);
+    hipLaunchKernelGGL(k_pack<S>, dim3(grid), dim3(kThreads), 0, s,
+                       static_cast<const S*>(padded_buf), static_cast<S*>(compact), g);
+  });
 }
 
 hipError_t launch_unpack(const void* compact, void* padded_buf, const Geom& g, int prec,
                          hipStream_t s) {
   const unsigned grid = grid_1d((long long)g.lx * g.ly * Q);
-  if (prec == kF64)
-    hipLaunchKernelGGL(k_unpack<double>, dim3(grid), dim3(kThreads), 0, s,
-                       static_cast<const double*>(compact), static_cast<double*>(padded_buf),
-                       g);
-  else
-    hipLaunchKernelGGL(k_unpack<float>, dim3(grid), dim3(kThreads), 0, s,
-                       static_cast<const float*>(compact), static_cast<float*>(padded_buf), g);
-  return hipGetLastError();
+  return by_precision(prec, [&](auto sv, auto) {
+    using S = decltype(sv);
+    hipLaunchKernelGGL(k_unpack<S>, dim3(grid), dim3(kThreads), 0, s,
+                       static_cast<const S*>(compact), static_cast<S*>(padded_buf), g);
+  });
 }
 
 hipError_t launch_populations_f64(const void* padded_buf, double* out, const Geom& g,
                                   const Phys& p, int prec, hipStream_t s) {
   const unsigned grid = grid_1d((long long)g.lx * g.ly * Q);
-  if (prec == kF64)
-    hipLaunchKernelGGL(k_populations_f64<double>, dim3(grid), dim3(kThreads), 0, s,
-                       static_cast<const double*>(padded_buf), out, g, 0.0);
-  else
-    hipLaunchKernelGGL(k_populations_f64<float>, dim3(grid), dim3(kThreads), 0, s,
-                       static_cast<const float*>(padded_buf), out, g, p.rho_ref);
-  return hipGetLastError();
+  return by_precision(prec, [&](auto sv, auto) {
+    using S = decltype(sv);
+    hipLaunchKernelGGL(k_populations_f64<S>, dim3(grid), dim3(kThreads), 0, s,
+                       static_cast<const S*>(padded_buf), out, g, p.rho_ref);
+  });
 }
 
 hipError_t launch_check(const void* src, unsigned int* flag, const Geom& g, const Phys& p,
                         int prec, hipStream_t s) {
   const Tiling t = make_tiling(g.lx, g.ly);
-  if (prec == kF64)
-    hipLaunchKernelGGL(k_check<double>, dim3(t.nb), dim3(kThreads), 0, s,
-                       static_cast<const double*>(src), flag, g, p, t.by, t.bx, t.nty, t.nb);
-  else
-    hipLaunchKernelGGL(k_check<float>, dim3(t.nb), dim3(kThreads), 0, s,
-                       static_cast<const float*>(src), flag, g, p, t.by, t.bx, t.nty, t.nb);
-  return hipGetLastError();
+  return by_precision(prec, [&](auto sv, auto) {
+    using S = decltype(sv);
+    hipLaunchKernelGGL(k_check<S>, dim3(t.nb), dim3(kThreads), 0, s, static_cast<const S*>(src),
+                       flag, g, p, t.by, t.bx, t.nty, t.nb);
+  });
 }
 
 int loss_ke_blocks(const Geom& g) { return int(make_tiling(g.lx, g.ly).nb); }

@@ -63,7 +63,8 @@ int check_lattice(const lb_lattice* lat) {
   if (!lat) return fail(LB_E_ARG, "lattice is NULL%s");
   if (lat->lx < 6 || lat->ly < 6) return fail(LB_E_ARG, "lx and ly must be >= 6%s");
   if (lat->lx > (1 << 24) || lat->ly > (1 << 24)) return fail(LB_E_ARG, "lattice too large%s");
-  if (lat->precision != LB_FP64 && lat->precision != LB_FP32_SHIFTED)
+  if (lat->precision != LB_FP64 && lat->precision != LB_FP32_SHIFTED &&
+      lat->precision != LB_FP32_SHIFTED_F32SUM)
     return fail(LB_E_ARG, "unknown precision%s");
   if (lat->ybc != LB_Y_WALLS && lat->ybc != LB_Y_PERIODIC) return fail(LB_E_ARG, "unknown ybc%s");
   if (lat->layout != LB_LAYOUT_SOA && lat->layout != LB_LAYOUT_COLUMN)
@@ -116,7 +117,7 @@ Phys make_phys(const lb_params& par, int prec) {
   p.dtheta = par.tau * (1.0 - par.tau) * (par.gx * par.gx + par.gy * par.gy) / 2.0;
   p.th_bottom = par.t_bottom - 1.0;
   p.th_top = par.t_top - 1.0;
-  p.rho_ref = prec == LB_FP32_SHIFTED ? par.rho_ref : 0.0;
+  p.rho_ref = prec == LB_FP64 ? 0.0 : par.rho_ref;
   return p;
 }
 
@@ -221,7 +222,7 @@ int lb_init(const lb_lattice* lat, const lb_params* par, void* workspace, size_t
     return fail(LB_E_WORKSPACE, "workspace must be 256-byte aligned%s");
   if (workspace_bytes < need) return fail(LB_E_WORKSPACE, "workspace too small%s");
   if (!rho0 || !ux0 || !uy0 || !T0) return fail(LB_E_ARG, "initial fields must not be NULL%s");
-  if (lat->precision == LB_FP32_SHIFTED && !(par->rho_ref >= 0))
+  if (lat->precision != LB_FP64 && !(par->rho_ref >= 0))
     return fail(LB_E_ARG, "rho_ref must be >= 0%s");
   lb_ctx* c = new (std::nothrow) lb_ctx;
   if (!c) return fail(LB_E_ARG, "out of host memory%s");
@@ -274,7 +275,7 @@ int lb_set_params(lb_ctx* ctx, const lb_params* par) {
   if (rc) return rc;
   rc = check_params(par);
   if (rc) return rc;
-  if (ctx->prec == LB_FP32_SHIFTED && par->rho_ref != ctx->par.rho_ref)
+  if (ctx->prec != LB_FP64 && par->rho_ref != ctx->par.rho_ref)
     return fail(LB_E_ARG, "rho_ref cannot change after lb_init%s");
   ctx->par = *par;
   ctx->p = make_phys(*par, ctx->prec);

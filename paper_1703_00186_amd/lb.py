@@ -17,7 +17,7 @@ from . import build as _build
 
 Q = 37
 
-LB_FP64, LB_FP32_SHIFTED = 0, 1
+LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM = 0, 1, 2
 LB_Y_WALLS, LB_Y_PERIODIC = 0, 1
 LB_LAYOUT_SOA, LB_LAYOUT_COLUMN = 0, 1
 LB_KERNEL_FUSED, LB_KERNEL_SPLIT = 0, 1
@@ -122,8 +122,8 @@ def make_params(tau=0.7, g=(0.0, -1e-4), t_bottom=1.5, t_top=0.5, rho_ref=1.0, r
                   float(rho_ref), int(regularize), k, int(check_finite), 0)
 
 
-def make_lattice(lx, ly, precision="fp64", ybc="walls", layout="soa") -> Lattice:
-    p = {"fp64": LB_FP64, "fp32s": LB_FP32_SHIFTED}[precision]
+def make_lattice(lx, ly, precision="fp64", ybc="walls", layout="column") -> Lattice:
+    p = {"fp64": LB_FP64, "fp32s": LB_FP32_SHIFTED, "fp32s_f32sum": LB_FP32_SHIFTED_F32SUM}[precision]
     y = {"walls": LB_Y_WALLS, "periodic": LB_Y_PERIODIC}[ybc]
     lay = {"soa": LB_LAYOUT_SOA, "column": LB_LAYOUT_COLUMN}[layout]
     return Lattice(int(lx), int(ly), p, y, lay, 0)
@@ -137,13 +137,14 @@ class LB:
     """
 
     def __init__(self, lx, ly, rho0, ux0, uy0, T0, *, precision="fp64", ybc="walls",
-                 layout="soa", device="cuda:0", **params):
+                 layout="column", device="cuda:0", **params):
         self.lib = load_library()
         self.device = torch.device(device)
         self.lx, self.ly = int(lx), int(ly)
         self.precision = precision
         self.lat = make_lattice(lx, ly, precision, ybc, layout)
-        self.par = make_params(**params)
+        self.params = dict(params)
+        self.par = make_params(**self.params)
         nbytes = ctypes.c_size_t(0)
         _check(self.lib.lb_workspace_bytes(ctypes.byref(self.lat), ctypes.byref(self.par),
                                            ctypes.byref(nbytes)))
@@ -179,8 +180,21 @@ class LB:
 
     # -- the step ------------------------------------------------------------
     def set_params(self, **params):
-        self.par = make_params(**params)
-        _check(self.lib.lb_set_params(self.ctx, ctypes.byref(self.par)))
+        """Updates the given parameters; the others keep their values."""
+        new = dict(self.params, **params)
+        par = make_params(**new)
+        _check(self.lib.lb_set_params(self.ctx, ctypes.byref(par)))
+        self.params, self.par = new, par
+
+    def reinit(self, rho0, ux0, uy0, T0):
+        """Restarts from f = f^eq(rho0, u0, T0) on the same workspace."""
+        fields = [self.field(a) for a in (rho0, ux0, uy0, T0)]
+        self.close()
+        nbytes = self.workspace.numel()
+        with torch.cuda.device(self.device):
+            _check(self.lib.lb_init(ctypes.byref(self.lat), ctypes.byref(self.par),
+                                    _ptr(self.workspace), nbytes, self._stream(),
+                                    *[_ptr(f) for f in fields], ctypes.byref(self.ctx)))
 
     def step(self, n: int = 1):
         self._sync_stream()
