@@ -164,6 +164,166 @@ def cpu_baseline(lx: int, ly: int, fields, steps: int) -> dict:
                       % (steps, lx, ly, dt, cpu)}
 
 
+def device_bytes_in_use(torch) -> int:
+    torch.cuda.synchronize()
+    return int(torch.cuda.memory_allocated())
+
+
+def run_configs(args, torch) -> list:
+    """One JSON record per workload of the build's configuration list:
+    parity (1), speed (2), FP32 precision (3), adjoint (4), production (5)."""
+    import numpy as np
+
+    import oracle
+    from paper_1703_00186_amd import adjoint, workload
+    from paper_1703_00186_amd.lb import LB
+
+    out = []
+    P = oracle.Params(tau=0.7, gx=0.0, gy=-1e-4, t_bottom=1.5, t_top=0.5)
+
+    # 1: 256 x 128 FP64, 50 steps on GPU and oracle
+    lx, ly, n = 256, 128, 50
+    f = workload.rt_fields(lx, ly, seed=workload.config_seed(1))[:4]
+    lb = LB(lx, ly, *f)
+    lb.step(n)
+    m = host_moments(lb, torch)
+    ref = oracle.moments(oracle.run(oracle.init_feq(*f), P, n))
+    out.append({"config": 1, "lattice": [lx, ly], "steps": n, "precision": "fp64",
+                "error_vs_oracle": field_errors(m, ref)})
+    log("configs: 1 %s" % out[-1])
+    del lb
+
+    # 3: 4096 x 4096, 2000 steps, FP32 shifted vs FP64 (GPU) + 256 x 256 vs oracle
+    lx, ly, n = 4096, 4096, args.c3_steps
+    f = workload.rt_fields(lx, ly, seed=workload.config_seed(3))[:4]
+    rec = {"config": 3, "lattice": [lx, ly], "steps": n}
+    ms = {}
+    for prec in ("fp64", "fp32s", "fp32s_f32sum"):
+        lb = LB(lx, ly, *f, precision=prec)
+        t = time_steps(lb, n, torch)
+        ms[prec] = host_moments(lb, torch)
+        rec[prec] = {"MLUPS": round(mlups(lx * ly * n, t), 1)}
+        del lb
+        torch.cuda.empty_cache()
+    for prec in ("fp32s", "fp32s_f32sum"):
+        rec[prec]["error_vs_fp64_gpu"] = field_errors(ms[prec], ms["fp64"])
+        rec[prec]["ratio_vs_fp64"] = round(rec[prec]["MLUPS"] / rec["fp64"]["MLUPS"], 3)
+    lxs = 256
+    fs = workload.rt_fields(lxs, lxs, seed=workload.config_seed(3))[:4]
+    lb = LB(lxs, lxs, *fs, precision="fp32s")
+    lb.step(n)
+    rec["fp32s"]["error_vs_oracle_256x256"] = field_errors(
+        host_moments(lb, torch), oracle.moments(oracle.run(oracle.init_feq(*fs), P, n)))
+    del lb
+    out.append(rec)
+    log("configs: 3 %s" % rec)
+
+    # 4: 512 x 512, 200 steps, gradient of KE w.r.t. 16 amplitudes, k = 20
+    lx, ly, n, k = 512, 512, 200, 20
+    seed = workload.config_seed(4)
+    rho, ux, uy, T, info = workload.rt_fields(lx, ly, seed=seed, mode="multimode")
+    lb = LB(lx, ly, rho, ux, uy, T)
+    fields = [torch.from_numpy(a).cuda().requires_grad_(True) for a in (rho, ux, uy, T)]
+    adjoint.kinetic_energy(lb, *fields, nsteps=40, checkpoint_every=k).backward()  # warm-up
+    fields = [torch.from_numpy(a).cuda().requires_grad_(True) for a in (rho, ux, uy, T)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ke = adjoint.kinetic_energy(lb, *fields, nsteps=n, checkpoint_every=k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ke.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = workload.amplitude_gradient(lx, ly, fields[0].grad.cpu().numpy(),
+                                    fields[3].grad.cpu().numpy(), seed=seed)
+    lb.reinit(rho, ux, uy, T)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    lb.step(n)
+    lb.loss_ke(with_lambda=False)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t3
+
+    def ke_of(amp):
+        ff = workload.rt_fields(lx, ly, seed=seed, mode="multimode", amplitudes=amp)[:4]
+        lb.reinit(*ff)
+        lb.step(n)
+        return float(lb.loss_ke(with_lambda=False)[0].cpu()[0])
+
+    fd = {}
+    for h in (1e-6, 1e-5):
+        gfd = np.zeros(16)
+        for j in range(16):
+            e = np.zeros(16)
+            e[j] = h
+            gfd[j] = (ke_of(info["amplitudes"] + e) - ke_of(info["amplitudes"] - e)) / (2 * h)
+        fd["%g" % h] = float(np.abs(g - gfd).max() / np.abs(gfd).max())
+    out.append({"config": 4, "lattice": [lx, ly], "steps": n, "checkpoint_every": k,
+                "KE": float(ke.detach().cpu()), "max_abs_grad": float(np.abs(g).max()),
+                "adjoint_vs_central_fd": fd, "forward_s": round(t_plain, 5),
+                "forward_with_checkpoints_s": round(t1 - t0, 5), "backward_s": round(t2 - t1, 5),
+                "backward_over_forward": round((t2 - t1) / t_plain, 3)})
+    log("configs: 4 %s" % out[-1])
+    del lb, fields
+    torch.cuda.empty_cache()
+
+    # 5: 8192 x 4096 production run: FP64 and FP32 shifted, then the adjoint of
+    # the last 100 FP64 steps (checkpoints every 20)
+    lx, ly, n, n_adj = 8192, 4096, args.c5_steps, 100
+    sites = lx * ly
+    seed = workload.config_seed(5)
+    rho, ux, uy, T, info = workload.rt_fields(lx, ly, seed=seed, mode="multimode")
+    rec = {"config": 5, "lattice": [lx, ly], "steps": n}
+    for prec in ("fp32s", "fp64"):
+        base = device_bytes_in_use(torch)
+        lb = LB(lx, ly, rho, ux, uy, T, precision=prec)
+        foot = device_bytes_in_use(torch) - base
+        t = time_steps(lb, n - (n_adj if prec == "fp64" else 0), torch)
+        steps_done = n - (n_adj if prec == "fp64" else 0)
+        v = mlups(sites * steps_done, t)
+        bps = bytes_per_site("fp64" if prec == "fp64" else "fp32")
+        rec[prec] = {"MLUPS": round(v, 1), "GB/s": round(bps * v * 1e6 / 1e9, 1),
+                     "hbm_frac": round(bps * v * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+                     "workspace_GB": round(foot / 1e9, 3), "steps_timed": steps_done}
+        if prec == "fp32s":
+            del lb
+            torch.cuda.empty_cache()
+    # adjoint of the last n_adj steps: d KE(final) / d (state at step n - n_adj)
+    k = 20
+    base = device_bytes_in_use(torch)
+    ckpts = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s0 in range(0, n_adj, k):
+        ckpts.append(lb.get_state())
+        lb.step(k)
+    ke, lam = lb.loss_ke(with_lambda=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tape = lb.new_tape(k)
+    spare = lb.new_populations(torch.float64)
+    for ck in reversed(ckpts):
+        lb.set_state(ck)
+        lb.step_record(k, tape)
+        for j in range(k - 1, -1, -1):
+            lb.adjoint_step(tape[j], lam, spare)
+            lam, spare = spare, lam
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    extra = device_bytes_in_use(torch) - base
+    rec["fp64"]["adjoint_last_steps"] = {
+        "steps": n_adj, "checkpoint_every": k, "forward_s": round(t1 - t0, 4),
+        "backward_s": round(t2 - t1, 4), "backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
+        "checkpoints_tape_lambda_GB": round(extra / 1e9, 3),
+        "lambda_norm": float(lam.norm().cpu())}
+    rec["peak_device_GB"] = round(torch.cuda.max_memory_allocated() / 1e9, 2)
+    del lb, ckpts, tape, spare, lam
+    torch.cuda.empty_cache()
+    out.append(rec)
+    log("configs: 5 %s" % rec)
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +337,11 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="time only the headline fused FP64 step (for profiling)")
+    ap.add_argument("--configs", action="store_true",
+                    help="run workloads 1, 3, 4 and 5 (parity, FP32, adjoint, production) "
+                         "and print one JSON record each instead of the headline line")
+    ap.add_argument("--c3-steps", type=int, default=2000)
+    ap.add_argument("--c5-steps", type=int, default=5000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scale reference)")
     args = ap.parse_args(argv)
@@ -191,6 +356,11 @@ def main(argv=None) -> int:
 
     from paper_1703_00186_amd import workload
     from paper_1703_00186_amd.lb import LB
+
+    if args.configs:
+        for rec in run_configs(args, torch):
+            print(json.dumps(rec), flush=True)
+        return 0
 
     lx, ly = args.lx, args.ly
     sites = lx * ly

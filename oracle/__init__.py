@@ -20,19 +20,25 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "d2q37_oracle.cpp")
-_LIB = os.path.join(_HERE, "liboracle_d2q37.so")
+_LIB = os.environ.get("ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle_d2q37.so")
 
 Q = 37
 
 
+def compile_library(src: str, out: str) -> str:
+    """g++ -O2, no FMA contraction, no fast-math, OpenMP."""
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
+           "-fopenmp", "-fPIC", "-shared", src, "-o", tmp, "-lquadmath"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
 def build_library(force: bool = True) -> str:
-    """Compile the oracle with g++ (-O2, no FMA contraction, OpenMP)."""
+    """Compile the oracle (ORACLE_LIBRARY overrides the library path to load)."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lquadmath"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+        compile_library(_SRC, _LIB)
     return _LIB
 
 
