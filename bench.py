@@ -39,6 +39,8 @@ def mlups(sites: int, seconds: float) -> float:
 
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_SUMMARY = os.path.join(PROFILES, "k_fused_fp64_rt1920x2048_hbm_traffic.md")
+VALU_SUMMARY = os.path.join(PROFILES, "k_fused_fp64_rt1920x2048_valu.md")
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 KERNEL_SOURCES = ["paper_1703_00186_amd/csrc/d2q37_kernels.hip",
                   "paper_1703_00186_amd/csrc/d2q37_device.h",
                   "paper_1703_00186_amd/csrc/d2q37_constants.h"]
@@ -53,22 +55,38 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def summary_values(path: str) -> dict:
+    """The '- key: value' lines of a committed profile summary, if the kernel
+    sources still hash to the value recorded with its counters."""
+    try:
+        vals = {}
+        for line in open(path):
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip()
+    except OSError:
+        return {}
+    return vals if vals.get("source_sha256_16") == kernel_source_hash() else {}
+
+
 def measured_traffic(lx: int, ly: int):
     """HBM bytes per fused launch from the committed counter summary, or None
     when the summary is missing, is for another lattice, or the kernel
     sources changed since the counters were taken."""
+    vals = summary_values(TRAFFIC_SUMMARY)
     try:
-        vals = {}
-        for line in open(TRAFFIC_SUMMARY):
-            if ":" in line and line.startswith("- "):
-                k, v = line[2:].split(":", 1)
-                vals[k.strip()] = v.strip()
-        if vals.get("source_sha256_16") != kernel_source_hash():
-            return None
         if vals.get("lattice") != "%dx%d" % (lx, ly):
             return None
         return float(vals["hbm_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+    except (KeyError, ValueError):
+        return None
+
+
+def counted_flop_per_site():
+    """FP64 flop per site counted by the VALU counters (None if stale)."""
+    try:
+        return float(summary_values(VALU_SUMMARY)["flop_per_site"])
+    except (KeyError, ValueError):
         return None
 
 
@@ -387,6 +405,12 @@ def main(argv=None) -> int:
                      "traffic": None, "kernel": "k_fused<double>",
                      "bytes_per_site": bytes_per_site("fp64")},
     }
+    fps = counted_flop_per_site()
+    if fps is not None:
+        tflops = fps * sites / (t / args.steps) / 1e12
+        out["fp64_compute"] = {"flop_per_site_counted": fps, "achieved": round(tflops, 2),
+                               "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4)}
     traffic = measured_traffic(lx, ly) if args.layout == "column" else None
     if traffic is not None:
         out["roofline"]["traffic"] = traffic
