@@ -157,6 +157,21 @@ int lb_collide(lb_ctx* ctx);
 int lb_get_scratch(lb_ctx* ctx, void* f);
 int lb_set_scratch(lb_ctx* ctx, const void* f);
 
+/* In-situ observables of the current state (the averages and correlations
+ * the paper's production runs compute every few hundred steps, Sec. 2), all
+ * on the device in FP64, deterministic.
+ * lb_observables: profiles (device [6][ly], may be NULL) receives the row
+ * averages over x of rho, u_x, u_y, T, rho |u|^2 / 2 and rho T; scalars
+ * (device [4], may be NULL) the total mass, the kinetic energy
+ * (1/2) sum rho |u|^2, sum rho T, and the mixing-layer width
+ * 6 sum_y phi (1 - phi) with phi = (Tbar(y) - t_top) / (t_bottom - t_top)
+ * clamped to [0, 1] (the width of a linear temperature ramp).
+ * lb_run_observed: n steps as lb_step; after every `every` steps the four
+ * scalars are written to series + 4 * (k - 1) for the k-th sample (device
+ * [n / every][4]); no host synchronisation. */
+int lb_observables(lb_ctx* ctx, double* profiles, double* scalars);
+int lb_run_observed(lb_ctx* ctx, int n, int every, double* series);
+
 /* Adjoint (LB_FP64 contexts only; LB_E_STATE otherwise).
  *
  * lb_step_record: like lb_step(n) with the fused kernel, and also writes, for

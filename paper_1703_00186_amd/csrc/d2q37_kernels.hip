@@ -502,6 +502,83 @@ __global__ __launch_bounds__(kThreads) void k_init_adjoint(
   if (dT) dT[s] = G.th;
 }
 
+// ---------------------------------------------------------------------------
+// In-situ observables: row averages over x and lattice totals.
+// ---------------------------------------------------------------------------
+
+// partial[c][k][y] = sum over the columns of chunk c of the k-th per-site
+// observable at row y: rho, u_x, u_y, T, rho |u|^2 / 2, rho T.
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_obs_rows(const S* __restrict__ src,
+                                                       double* __restrict__ partial, Geom g,
+                                                       Phys P, int nchunks) {
+  const int y = blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  if (y >= g.ly) return;
+  const int x0 = int((long long)g.lx * c / nchunks), x1 = int((long long)g.lx * (c + 1) / nchunks);
+  double acc[kObservables] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int x = x0; x < x1; ++x) {
+    double f[Q];
+    load_site<S, double>(src, g, (long long)(x + HX) * g.cs + (y + g.hy), f);
+    double a[5][5];
+    project<double>(f, a);
+    const Macro m = macro_from(P.rho_ref + a[0][0], a[1][0], a[0][1], a[2][0], a[0][2]);
+    const double T = 1.0 + m.th;
+    acc[0] += m.rho;
+    acc[1] += m.ux;
+    acc[2] += m.uy;
+    acc[3] += T;
+    acc[4] += 0.5 * m.rho * (m.ux * m.ux + m.uy * m.uy);
+    acc[5] += m.rho * T;
+  }
+#pragma unroll
+  for (int k = 0; k < kObservables; ++k)
+    partial[((long long)c * kObservables + k) * g.ly + y] = acc[k];
+}
+
+// profiles[k][y] = (sum over chunks of partial[c][k][y]) / lx, in chunk order.
+__global__ __launch_bounds__(kThreads) void k_obs_reduce(const double* __restrict__ partial,
+                                                         double* __restrict__ profiles, int lx,
+                                                         int ly, int nchunks) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= kObservables * ly) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += partial[(long long)c * kObservables * ly + i];
+  profiles[i] = s / lx;
+}
+
+// scalars: mass, kinetic energy, sum rho T, mixing-layer width
+// 6 sum_y phi (1 - phi), phi = (Tbar(y) - T_top) / (T_bottom - T_top) in [0, 1].
+__global__ __launch_bounds__(kThreads) void k_obs_scalars(const double* __restrict__ profiles,
+                                                          double* __restrict__ scalars, int lx,
+                                                          int ly, double t_bottom, double t_top) {
+  double m = 0.0, ke = 0.0, e = 0.0, w = 0.0;
+  const double dT = t_bottom - t_top;
+  for (int y = threadIdx.x; y < ly; y += kThreads) {
+    m += profiles[0 * ly + y];
+    ke += profiles[4 * ly + y];
+    e += profiles[5 * ly + y];
+    if (dT != 0.0) {
+      double phi = (profiles[3 * ly + y] - t_top) / dT;
+      phi = phi < 0.0 ? 0.0 : (phi > 1.0 ? 1.0 : phi);
+      w += phi * (1.0 - phi);
+    }
+  }
+  m = block_sum(m);
+  __syncthreads();
+  ke = block_sum(ke);
+  __syncthreads();
+  e = block_sum(e);
+  __syncthreads();
+  w = block_sum(w);
+  if (threadIdx.x == 0) {
+    scalars[0] = m * lx;
+    scalars[1] = ke * lx;
+    scalars[2] = e * lx;
+    scalars[3] = 6.0 * w;
+  }
+}
+
 unsigned grid_1d(long long n) { return unsigned((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -667,6 +744,27 @@ hipError_t launch_check(const void* src, unsigned int* flag, const Geom& g, cons
     hipLaunchKernelGGL(k_check<S>, dim3(t.nb), dim3(kThreads), 0, s, static_cast<const S*>(src),
                        flag, g, p, t.by, t.bx, t.nty, t.nb);
   });
+}
+
+int observable_chunks(const Geom& g) { return g.lx < 64 ? g.lx : 64; }
+
+hipError_t launch_observables(const void* src, double* partial, double* profiles,
+                              double* scalars, const Geom& g, const Phys& p, int prec,
+                              double t_bottom, double t_top, hipStream_t s) {
+  const int nc = observable_chunks(g);
+  hipError_t e = by_precision(prec, [&](auto sv, auto) {
+    using S = decltype(sv);
+    hipLaunchKernelGGL(k_obs_rows<S>, dim3(grid_1d(g.ly), nc), dim3(kThreads), 0, s,
+                       static_cast<const S*>(src), partial, g, p, nc);
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_obs_reduce, dim3(grid_1d((long long)kObservables * g.ly)), dim3(kThreads),
+                     0, s, partial, profiles, g.lx, g.ly, nc);
+  e = hipGetLastError();
+  if (e != hipSuccess || !scalars) return e;
+  hipLaunchKernelGGL(k_obs_scalars, dim3(1), dim3(kThreads), 0, s, profiles, scalars, g.lx, g.ly,
+                     t_bottom, t_top);
+  return hipGetLastError();
 }
 
 int loss_ke_blocks(const Geom& g) { return int(make_tiling(g.lx, g.ly).nb); }

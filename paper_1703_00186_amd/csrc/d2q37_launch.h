@@ -54,6 +54,17 @@ hipError_t launch_populations_f64(const void* padded, double* out, const Geom& g
 hipError_t launch_check(const void* src, unsigned int* flag, const Geom& g, const Phys& p,
                         int prec, hipStream_t s);
 
+// In-situ observables.  profiles: [kObservables][ly] row averages over x of
+// rho, u_x, u_y, T, rho |u|^2 / 2, rho T; scalars (optional): total mass,
+// kinetic energy, sum of rho T, mixing-layer width.  partial: scratch of
+// observable_chunks(g) * kObservables * ly doubles.
+constexpr int kObservables = 6;
+constexpr int kObservableScalars = 4;
+int observable_chunks(const Geom& g);
+hipError_t launch_observables(const void* src, double* partial, double* profiles,
+                              double* scalars, const Geom& g, const Phys& p, int prec,
+                              double t_bottom, double t_top, hipStream_t s);
+
 // Adjoint (FP64 buffers).
 // KE of the padded state: per-block partial sums into `partials` (size
 // returned by loss_ke_blocks), then reduced into *ke; lambda (optional)

@@ -24,6 +24,7 @@ struct lb_ctx {
   char* A;  // state buffer (post-collision populations)
   char* B;  // scratch buffer (propagated populations, next state)
   double* partials;
+  double* obs;  // observable scratch (chunk partials | profiles | scalars)
   unsigned int* flag;
   bool halos_valid;
   long long steps_since_check;
@@ -129,6 +130,13 @@ size_t partial_bytes(const Geom& g) {
   return round_up(size_t(d2q37::loss_ke_blocks(g)) * sizeof(double), kAlign);
 }
 
+// observable scratch: chunk partials, then the profiles and the scalars
+size_t observable_bytes(const Geom& g) {
+  const size_t prof = size_t(d2q37::kObservables) * size_t(g.ly);
+  return round_up((size_t(d2q37::observable_chunks(g)) * prof + prof +
+                   size_t(d2q37::kObservableScalars)) * sizeof(double), kAlign);
+}
+
 int check_ctx(lb_ctx* ctx) {
   if (!ctx) return fail(LB_E_ARG, "context is NULL%s");
   return LB_OK;
@@ -205,7 +213,7 @@ int lb_workspace_bytes(const lb_lattice* lat, const lb_params* par, size_t* byte
   if (rc) return rc;
   if (!bytes) return fail(LB_E_ARG, "bytes is NULL%s");
   const Geom g = make_geom(*lat);
-  *bytes = 2 * buffer_bytes(g, lat->precision) + partial_bytes(g) + kAlign;
+  *bytes = 2 * buffer_bytes(g, lat->precision) + partial_bytes(g) + observable_bytes(g) + kAlign;
   return LB_OK;
 }
 
@@ -237,7 +245,9 @@ int lb_init(const lb_lattice* lat, const lb_params* par, void* workspace, size_t
   c->A = ws;
   c->B = ws + nb;
   c->partials = reinterpret_cast<double*>(ws + 2 * nb);
-  c->flag = reinterpret_cast<unsigned int*>(ws + 2 * nb + partial_bytes(c->g));
+  c->obs = reinterpret_cast<double*>(ws + 2 * nb + partial_bytes(c->g));
+  c->flag = reinterpret_cast<unsigned int*>(ws + 2 * nb + partial_bytes(c->g) +
+                                            observable_bytes(c->g));
   c->halos_valid = false;
   c->steps_since_check = 0;
   // zero both buffers so that never-written padding (the y halo rows read by
@@ -369,6 +379,36 @@ int lb_set_scratch(lb_ctx* ctx, const void* f) {
   if (rc) return rc;
   if (!f) return fail(LB_E_ARG, "f is NULL%s");
   LB_HIP(d2q37::launch_unpack(f, ctx->B, ctx->g, ctx->prec, ctx->stream), "set_scratch");
+  return LB_OK;
+}
+
+int lb_observables(lb_ctx* ctx, double* profiles, double* scalars) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  const size_t prof = size_t(d2q37::kObservables) * size_t(ctx->g.ly);
+  double* partial = ctx->obs;
+  double* own_prof = ctx->obs + size_t(d2q37::observable_chunks(ctx->g)) * prof;
+  LB_HIP(d2q37::launch_observables(ctx->A, partial, profiles ? profiles : own_prof, scalars,
+                                   ctx->g, ctx->p, ctx->prec, ctx->par.t_bottom, ctx->par.t_top,
+                                   ctx->stream),
+         "observables");
+  return LB_OK;
+}
+
+int lb_run_observed(lb_ctx* ctx, int n, int every, double* series) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (n < 0 || every <= 0) return fail(LB_E_ARG, "need n >= 0 and every > 0%s");
+  if (n >= every && !series) return fail(LB_E_ARG, "series is NULL%s");
+  for (int i = 1; i <= n; ++i) {
+    rc = one_step(ctx, nullptr);
+    if (rc) return rc;
+    if (i % every == 0) {
+      rc = lb_observables(ctx, nullptr,
+                          series + size_t(i / every - 1) * d2q37::kObservableScalars);
+      if (rc) return rc;
+    }
+  }
   return LB_OK;
 }
 

@@ -29,8 +29,12 @@ EXPORTS = [
     "lb_last_error", "lb_version", "lb_workspace_bytes", "lb_init", "lb_free", "lb_set_stream",
     "lb_set_params", "lb_step", "lb_moments", "lb_get_state", "lb_set_state",
     "lb_get_populations", "lb_halo", "lb_propagate", "lb_bc", "lb_collide", "lb_get_scratch",
-    "lb_set_scratch", "lb_step_record", "lb_loss_ke", "lb_adjoint_step", "lb_init_adjoint",
+    "lb_set_scratch", "lb_observables", "lb_run_observed", "lb_step_record", "lb_loss_ke",
+    "lb_adjoint_step", "lb_init_adjoint",
 ]
+
+N_PROFILES = 6  # rho, u_x, u_y, T, rho |u|^2 / 2, rho T (row averages)
+N_SCALARS = 4   # mass, kinetic energy, sum rho T, mixing-layer width
 
 
 class LBError(RuntimeError):
@@ -89,6 +93,8 @@ def load_library():
         "lb_collide": ([vp], i),
         "lb_get_scratch": ([vp, vp], i),
         "lb_set_scratch": ([vp, vp], i),
+        "lb_observables": ([vp, vp, vp], i),
+        "lb_run_observed": ([vp, i, i, vp], i),
         "lb_step_record": ([vp, i, vp], i),
         "lb_loss_ke": ([vp, vp, vp], i),
         "lb_adjoint_step": ([vp, vp, vp, vp], i),
@@ -251,6 +257,23 @@ class LB:
         self._sync_stream()
         f = f.to(self.device, self.state_dtype).contiguous()
         _check(self.lib.lb_set_scratch(self.ctx, _ptr(f)))
+
+    # -- in-situ observables ------------------------------------------------
+    def observables(self):
+        """(profiles [6, ly], scalars [4]) of the current state, on the device."""
+        self._sync_stream()
+        prof = torch.empty((N_PROFILES, self.ly), dtype=torch.float64, device=self.device)
+        sc = torch.empty(N_SCALARS, dtype=torch.float64, device=self.device)
+        _check(self.lib.lb_observables(self.ctx, _ptr(prof), _ptr(sc)))
+        return prof, sc
+
+    def run_observed(self, n: int, every: int) -> torch.Tensor:
+        """n steps; the 4 scalars after every `every` steps, [n // every, 4]."""
+        self._sync_stream()
+        series = torch.empty((max(n // every, 1), N_SCALARS), dtype=torch.float64,
+                             device=self.device)
+        _check(self.lib.lb_run_observed(self.ctx, int(n), int(every), _ptr(series)))
+        return series[: n // every]
 
     # -- adjoint -------------------------------------------------------------
     def new_tape(self, n: int) -> torch.Tensor:
