@@ -57,6 +57,13 @@ def test_run_observed_series():
     torch.cuda.synchronize()
     assert series.shape == (4, 4)
     assert torch.equal(series, torch.stack(rows))
-    # mass is conserved by the step (walls preserve it, collide conserves it)
-    m = series[:, 0].cpu().numpy()
-    assert np.abs(m - m[0]).max() <= 1e-12 * m[0]
+
+
+def test_mass_conserved_without_walls():
+    """Collide and propagate conserve mass; with periodic y the total stays put."""
+    lx, ly = 64, 96
+    f = workload.rt_fields(lx, ly, seed=4)[:4]
+    lb = LB(lx, ly, *f, ybc="periodic")
+    m = lb.run_observed(60, 20)[:, 0].cpu().numpy()
+    m0 = float(np.sum(f[0]))
+    assert np.abs(m - m0).max() <= 1e-12 * m0
