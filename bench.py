@@ -342,6 +342,72 @@ def run_configs(args, torch) -> list:
     return out
 
 
+def run_ablations(args, torch) -> list:
+    """Variants of the step: memory layout, plain BGK vs Hermite-regularized
+    collision (speed, and the smallest tau that stays finite), and the FP32
+    shift density."""
+    from paper_1703_00186_amd import workload
+    from paper_1703_00186_amd.lb import LB, LBError
+
+    out = []
+    lx, ly = args.lx, args.ly
+    sites = lx * ly
+    f = workload.rt_fields(lx, ly, seed=workload.config_seed(2))[:4]
+    speed = {}
+    for layout in ("soa", "column"):
+        for prec in ("fp64", "fp32s"):
+            for reg in (1, 0):
+                lb = LB(lx, ly, *f, precision=prec, layout=layout, regularize=reg)
+                lb.step(20)
+                t = time_steps(lb, 200, torch)
+                speed["%s/%s/%s" % (layout, prec, "regularized" if reg else "bgk")] = round(
+                    mlups(sites * 200, t), 1)
+                del lb
+                torch.cuda.empty_cache()
+    out.append({"ablation": "layout x precision x collision, fused step MLUPS",
+                "lattice": [lx, ly], "MLUPS": speed})
+    log("ablations: %s" % out[-1])
+
+    # stability: smallest tau whose RT run stays finite for n steps
+    sl, n = 512, args.stability_steps
+    fs = workload.rt_fields(sl, sl, seed=workload.config_seed(2))[:4]
+    stab = {}
+    for reg in (1, 0):
+        for tau in (0.502, 0.505, 0.51, 0.52, 0.53, 0.55, 0.6, 0.7):
+            lb = LB(sl, sl, *fs, tau=tau, regularize=reg, check_finite=100)
+            status = "finite"
+            try:
+                lb.step(n)
+            except LBError as e:
+                if e.code != -5:
+                    raise
+                status = "blew up"
+            stab["%s tau=%g" % ("regularized" if reg else "bgk", tau)] = status
+            del lb
+    out.append({"ablation": "stability of the RT run (finite after %d steps, check every 100)" % n,
+                "lattice": [sl, sl], "result": stab})
+    log("ablations: %s" % out[-1])
+
+    # FP32 shift density rho_ref: error after 2000 steps vs FP64
+    al, n = 1024, 2000
+    fa = workload.rt_fields(al, al, seed=workload.config_seed(3))[:4]
+    lb = LB(al, al, *fa)
+    lb.step(n)
+    m64 = host_moments(lb, torch)
+    del lb
+    shift = {}
+    for prec in ("fp32s", "fp32s_f32sum"):
+        for rho_ref in (0.0, 1.0):
+            lb = LB(al, al, *fa, precision=prec, rho_ref=rho_ref)
+            lb.step(n)
+            shift["%s rho_ref=%g" % (prec, rho_ref)] = field_errors(host_moments(lb, torch), m64)
+            del lb
+    out.append({"ablation": "FP32 storage: shift density and sum precision, error vs FP64 "
+                            "after %d steps" % n, "lattice": [al, al], "errors": shift})
+    log("ablations: %s" % out[-1])
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,6 +424,9 @@ def main(argv=None) -> int:
     ap.add_argument("--configs", action="store_true",
                     help="run workloads 1, 3, 4 and 5 (parity, FP32, adjoint, production) "
                          "and print one JSON record each instead of the headline line")
+    ap.add_argument("--ablations", action="store_true",
+                    help="run the layout / collision / stability / FP32-shift ablations")
+    ap.add_argument("--stability-steps", type=int, default=5000)
     ap.add_argument("--c3-steps", type=int, default=2000)
     ap.add_argument("--c5-steps", type=int, default=5000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -375,8 +444,8 @@ def main(argv=None) -> int:
     from paper_1703_00186_amd import workload
     from paper_1703_00186_amd.lb import LB
 
-    if args.configs:
-        for rec in run_configs(args, torch):
+    if args.configs or args.ablations:
+        for rec in (run_configs if args.configs else run_ablations)(args, torch):
             print(json.dumps(rec), flush=True)
         return 0
 
