@@ -521,6 +521,31 @@ def main(argv=None) -> int:
             log("bench: fused %s %.1f MLUPS (x%.2f), errors %s" % (prec, v32, v32 / value, errs))
             del lb32
             torch.cuda.empty_cache()
+    if not args.no_extras:
+        # launch-bound small lattice: eager launches vs one graph of 100 steps
+        sl, sh = 256, 128
+        fsm = workload.rt_fields(sl, sh, seed=workload.config_seed(1))[:4]
+        lbs = LB(sl, sh, *fsm)
+        lbs.step(20)
+        te = time_steps(lbs, 1000, torch)
+        graph = lbs.capture(100)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        tg = e0.elapsed_time(e1) / 1e3
+        out["small_lattice_256x128"] = {
+            "eager_MLUPS": round(mlups(sl * sh * 1000, te), 1),
+            "graph_MLUPS": round(mlups(sl * sh * 1000, tg), 1),
+            "eager_us_per_step": round(te / 1000 * 1e6, 2),
+            "graph_us_per_step": round(tg / 1000 * 1e6, 2)}
+        log("bench: 256x128 eager %.2f us/step, graph %.2f us/step" % (te / 1000 * 1e6,
+                                                                     tg / 1000 * 1e6))
+        del graph, lbs
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle (%d steps)" % args.cpu_steps)
         out["cpu_baseline"] = cpu_baseline(lx, ly, fields, args.cpu_steps)

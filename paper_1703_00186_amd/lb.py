@@ -206,6 +206,27 @@ class LB:
         self._sync_stream()
         _check(self.lib.lb_step(self.ctx, int(n)))
 
+    def capture(self, n: int = 2, pool=None):
+        """Records n (even) fused steps into a CUDA/HIP graph on a side
+        stream; graph.replay() then advances this lattice by n steps.
+
+        The buffers swap once per step, so an even n returns the state to the
+        buffer it started in, which is what lets the same graph run again.
+        Only the fused path without check_finite is capturable.
+        """
+        if n <= 0 or n % 2:
+            raise ValueError("n must be a positive even number")
+        if self.params.get("check_finite", 0) or self.params.get("kernel", "fused") != "fused":
+            raise ValueError("capture needs kernel='fused' and check_finite=0")
+        self.step(2)  # halos valid, buffers settled before capture
+        torch.cuda.synchronize(self.device)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, pool=pool):
+            self.step(n)
+        torch.cuda.synchronize(self.device)
+        self._sync_stream()
+        return graph
+
     def moments(self):
         self._sync_stream()
         out = [torch.empty((self.lx, self.ly), dtype=torch.float64, device=self.device)
