@@ -1,0 +1,65 @@
+"""Parity at the benchmark sizes, in the benchmark's launch configuration.
+
+The whole lattice is too large for the oracle to step, so the oracle evaluates
+one step at sampled sites only (propagate from the neighbours, bc, collide),
+starting from the GPU's own state; the GPU's next state must agree at those
+sites.  Samples: random sites, every wall row next to the periodic edges, and
+the rows on both sides of the 256-row tile boundaries.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import gpu_available
+from paper_1703_00186_amd import workload
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+    from paper_1703_00186_amd.lb import LB
+
+
+def sample_sites(lx, ly, n_random=4096, seed=0):
+    rng = np.random.default_rng(seed)
+    xs = list(rng.integers(0, lx, n_random))
+    ys = list(rng.integers(0, ly, n_random))
+    for x in (0, 1, 2, 3, lx // 2, lx - 4, lx - 3, lx - 2, lx - 1):
+        for y in (0, 1, 2, 3, ly - 4, ly - 3, ly - 2, ly - 1):
+            xs.append(x)
+            ys.append(y)
+    for y in range(255, ly, 256):
+        for x in (0, lx // 3, lx - 1):
+            xs += [x, x]
+            ys += [y, min(y + 1, ly - 1)]
+    return np.array(xs, np.int32), np.array(ys, np.int32)
+
+
+def oparams():
+    return oracle.Params(tau=0.7, gx=0.0, gy=-1e-4, t_bottom=1.5, t_top=0.5)
+
+
+@pytest.mark.parametrize("lx,ly,precision,mode,warm", [
+    (1920, 2048, "fp64", "sinusoid", 50),
+    (4096, 4096, "fp32s", "sinusoid", 20),
+    (8192, 4096, "fp64", "multimode", 10),
+])
+def test_one_step_at_sampled_sites(lx, ly, precision, mode, warm):
+    seed = workload.config_seed({2048: 2, 4096: 3 if lx == 4096 else 5}[ly])
+    f = workload.rt_fields(lx, ly, seed=seed, mode=mode)[:4]
+    lb = LB(lx, ly, *f, precision=precision)
+    lb.step(warm)
+    state = lb.populations().cpu().numpy()  # true populations, FP64
+    lb.step(1)
+    torch.cuda.synchronize()
+    nxt = lb.populations().cpu().numpy()
+    xs, ys = sample_sites(lx, ly)
+    ref = oracle.step_sites(state, oparams(), xs, ys)
+    got = nxt[:, xs, ys].T
+    # FP64: rounding of one step (1e-13 of the scale); FP32 storage: one
+    # rounding of each stored population (2^-24) plus the input's own rounding
+    tol = 1e-13 if precision == "fp64" else 3e-7
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    del lb
+    torch.cuda.empty_cache()
