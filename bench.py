@@ -187,9 +187,10 @@ def device_bytes_in_use(torch) -> int:
     return int(torch.cuda.memory_allocated())
 
 
-def run_configs(args, torch) -> list:
-    """One JSON record per workload of the build's configuration list:
-    parity (1), speed (2), FP32 precision (3), adjoint (4), production (5)."""
+def run_workloads(args, torch) -> list:
+    """One JSON record per workload: parity (256 x 128), FP32 precision
+    (4096 x 4096), adjoint (512 x 512) and production (8192 x 4096); the
+    1920 x 2048 speed workload is the headline line."""
     import numpy as np
 
     import oracle
@@ -199,22 +200,22 @@ def run_configs(args, torch) -> list:
     out = []
     P = oracle.Params(tau=0.7, gx=0.0, gy=-1e-4, t_bottom=1.5, t_top=0.5)
 
-    # 1: 256 x 128 FP64, 50 steps on GPU and oracle
+    # parity: 256 x 128 FP64, 50 steps on GPU and oracle
     lx, ly, n = 256, 128, 50
     f = workload.rt_fields(lx, ly, seed=workload.config_seed(1))[:4]
     lb = LB(lx, ly, *f)
     lb.step(n)
     m = host_moments(lb, torch)
     ref = oracle.moments(oracle.run(oracle.init_feq(*f), P, n))
-    out.append({"config": 1, "lattice": [lx, ly], "steps": n, "precision": "fp64",
+    out.append({"workload": "parity 256x128", "lattice": [lx, ly], "steps": n, "precision": "fp64",
                 "error_vs_oracle": field_errors(m, ref)})
-    log("configs: 1 %s" % out[-1])
+    log("workloads: %s" % out[-1])
     del lb
 
-    # 3: 4096 x 4096, 2000 steps, FP32 shifted vs FP64 (GPU) + 256 x 256 vs oracle
+    # FP32 precision: 4096 x 4096, 2000 steps, FP32 shifted vs FP64 (GPU) + 256 x 256 vs oracle
     lx, ly, n = 4096, 4096, args.c3_steps
     f = workload.rt_fields(lx, ly, seed=workload.config_seed(3))[:4]
-    rec = {"config": 3, "lattice": [lx, ly], "steps": n}
+    rec = {"workload": "FP32 precision 4096x4096", "lattice": [lx, ly], "steps": n}
     ms = {}
     for prec in ("fp64", "fp32s", "fp32s_f32sum"):
         lb = LB(lx, ly, *f, precision=prec)
@@ -234,9 +235,9 @@ def run_configs(args, torch) -> list:
         host_moments(lb, torch), oracle.moments(oracle.run(oracle.init_feq(*fs), P, n)))
     del lb
     out.append(rec)
-    log("configs: 3 %s" % rec)
+    log("workloads: %s" % rec)
 
-    # 4: 512 x 512, 200 steps, gradient of KE w.r.t. 16 amplitudes, k = 20
+    # adjoint: 512 x 512, 200 steps, gradient of KE w.r.t. 16 amplitudes, k = 20
     lx, ly, n, k = 512, 512, 200, 20
     seed = workload.config_seed(4)
     rho, ux, uy, T, info = workload.rt_fields(lx, ly, seed=seed, mode="multimode")
@@ -276,22 +277,22 @@ def run_configs(args, torch) -> list:
             e[j] = h
             gfd[j] = (ke_of(info["amplitudes"] + e) - ke_of(info["amplitudes"] - e)) / (2 * h)
         fd["%g" % h] = float(np.abs(g - gfd).max() / np.abs(gfd).max())
-    out.append({"config": 4, "lattice": [lx, ly], "steps": n, "checkpoint_every": k,
+    out.append({"workload": "adjoint 512x512", "lattice": [lx, ly], "steps": n, "checkpoint_every": k,
                 "KE": float(ke.detach().cpu()), "max_abs_grad": float(np.abs(g).max()),
                 "adjoint_vs_central_fd": fd, "forward_s": round(t_plain, 5),
                 "forward_with_checkpoints_s": round(t1 - t0, 5), "backward_s": round(t2 - t1, 5),
                 "backward_over_forward": round((t2 - t1) / t_plain, 3)})
-    log("configs: 4 %s" % out[-1])
+    log("workloads: %s" % out[-1])
     del lb, fields
     torch.cuda.empty_cache()
 
-    # 5: 8192 x 4096 production run: FP64 and FP32 shifted, then the adjoint of
+    # production: 8192 x 4096, FP64 and FP32 shifted, then the adjoint of
     # the last 100 FP64 steps (checkpoints every 20)
     lx, ly, n, n_adj = 8192, 4096, args.c5_steps, 100
     sites = lx * ly
     seed = workload.config_seed(5)
     rho, ux, uy, T, info = workload.rt_fields(lx, ly, seed=seed, mode="multimode")
-    rec = {"config": 5, "lattice": [lx, ly], "steps": n}
+    rec = {"workload": "production 8192x4096", "lattice": [lx, ly], "steps": n}
     for prec in ("fp32s", "fp64"):
         base = device_bytes_in_use(torch)
         lb = LB(lx, ly, rho, ux, uy, T, precision=prec)
@@ -338,7 +339,7 @@ def run_configs(args, torch) -> list:
     del lb, ckpts, tape, spare, lam
     torch.cuda.empty_cache()
     out.append(rec)
-    log("configs: 5 %s" % rec)
+    log("workloads: %s" % rec)
     return out
 
 
@@ -444,8 +445,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="time only the headline fused FP64 step (for profiling)")
-    ap.add_argument("--configs", action="store_true",
-                    help="run workloads 1, 3, 4 and 5 (parity, FP32, adjoint, production) "
+    ap.add_argument("--workloads", action="store_true",
+                    help="run the parity, FP32-precision, adjoint and production workloads "
                          "and print one JSON record each instead of the headline line")
     ap.add_argument("--ablations", action="store_true",
                     help="run the layout / collision / stability / FP32-shift ablations")
@@ -467,8 +468,8 @@ def main(argv=None) -> int:
     from paper_1703_00186_amd import workload
     from paper_1703_00186_amd.lb import LB
 
-    if args.configs or args.ablations:
-        for rec in (run_configs if args.configs else run_ablations)(args, torch):
+    if args.workloads or args.ablations:
+        for rec in (run_workloads if args.workloads else run_ablations)(args, torch):
             print(json.dumps(rec), flush=True)
         return 0
 

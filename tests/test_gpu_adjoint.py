@@ -143,7 +143,7 @@ def test_gradient_matches_oracle_complex_step_64():
     assert err <= 1e-10, (err, g_gpu, g_cs)
 
 
-def test_config4_gradient_vs_finite_differences_and_cost():
+def test_gradient_512_vs_finite_differences_and_cost():
     lx, ly, nsteps, every = 512, 512, 200, 20
     seed = workload.config_seed(4)
     rho, ux, uy, T, info = workload.rt_fields(lx, ly, seed=seed, mode="multimode")
@@ -179,7 +179,7 @@ def test_config4_gradient_vs_finite_differences_and_cost():
             g_fd[k] = (ke_of(a0 + e) - ke_of(a0 - e)) / (2 * h)
         errs[h] = np.abs(g_adj - g_fd).max() / np.abs(g_fd).max()
     noise_floor = 16 * np.finfo(float).eps * ke / 1e-6 / np.abs(g_adj).max()
-    print("config4: KE %.6e, max|g| %.3e, adjoint vs FD max rel %.2e (h=1e-6, noise floor "
+    print("adjoint 512x512: KE %.6e, max|g| %.3e, adjoint vs FD max rel %.2e (h=1e-6, noise floor "
           "%.1e), %.2e (h=1e-5); forward %.4f s (with checkpoints %.4f s), backward %.4f s, "
           "ratio %.2f" % (ke, np.abs(g_adj).max(), errs[1e-6], noise_floor, errs[1e-5], t_fwd,
                           t_fwd_ckpt, t_bwd, t_bwd / t_fwd))

@@ -98,7 +98,7 @@ def test_collide(layout, regularize):
 
 @pytest.mark.parametrize("kernel", ["fused", "split"])
 @pytest.mark.parametrize("layout", ["soa", "column"])
-def test_rt_50_steps_config1(kernel, layout):
+def test_rt_256x128_50_steps(kernel, layout):
     """256 x 128 Rayleigh-Taylor, 50 steps: every field within 1e-12."""
     lx, ly = 256, 128
     lb, fields = make(lx, ly, kernel=kernel, layout=layout)
