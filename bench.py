@@ -191,29 +191,47 @@ def run_workloads(args, torch) -> list:
     """One JSON record per workload: parity (256 x 128), FP32 precision
     (4096 x 4096), adjoint (512 x 512) and production (8192 x 4096); the
     1920 x 2048 speed workload is the headline line."""
-    import numpy as np
-
     import oracle
-    from paper_1703_00186_amd import adjoint, workload
-    from paper_1703_00186_amd.lb import LB
 
     out = []
     P = oracle.Params(tau=0.7, gx=0.0, gy=-1e-4, t_bottom=1.5, t_top=0.5)
+    todo = set(args.workloads or ["parity", "fp32", "adjoint", "production"])
+    if "parity" in todo:
+        out.append(_parity_workload(P, torch))
+    if "fp32" in todo:
+        out.append(_fp32_workload(args, P, torch))
+    if "adjoint" in todo:
+        out.append(_adjoint_workload(torch))
+    if "production" in todo:
+        out.append(_production_workload(args, torch))
+    return out
 
-    # parity: 256 x 128 FP64, 50 steps on GPU and oracle
+
+def _parity_workload(P, torch) -> dict:
+    import oracle
+    from paper_1703_00186_amd import workload
+    from paper_1703_00186_amd.lb import LB
+
     lx, ly, n = 256, 128, 50
     f = workload.rt_fields(lx, ly, seed=workload.config_seed(1))[:4]
     lb = LB(lx, ly, *f)
     lb.step(n)
     m = host_moments(lb, torch)
     ref = oracle.moments(oracle.run(oracle.init_feq(*f), P, n))
-    out.append({"workload": "parity 256x128", "lattice": [lx, ly], "steps": n, "precision": "fp64",
-                "error_vs_oracle": field_errors(m, ref)})
-    log("workloads: %s" % out[-1])
-    del lb
+    rec = {"workload": "parity 256x128", "lattice": [lx, ly], "steps": n, "precision": "fp64",
+           "error_vs_oracle": field_errors(m, ref)}
+    log("workloads: %s" % rec)
+    return rec
 
-    # FP32 precision: 4096 x 4096, 2000 steps, FP32 shifted vs FP64 (GPU) + 256 x 256 vs oracle
-    lx, ly, n = 4096, 4096, args.c3_steps
+
+def _fp32_workload(args, P, torch) -> dict:
+    """4096 x 4096, FP32 shifted (both sum precisions) vs FP64 on the GPU,
+    plus FP32 shifted vs the oracle on 256 x 256."""
+    import oracle
+    from paper_1703_00186_amd import workload
+    from paper_1703_00186_amd.lb import LB
+
+    lx, ly, n = 4096, 4096, args.fp32_steps
     f = workload.rt_fields(lx, ly, seed=workload.config_seed(3))[:4]
     rec = {"workload": "FP32 precision 4096x4096", "lattice": [lx, ly], "steps": n}
     ms = {}
@@ -234,10 +252,20 @@ def run_workloads(args, torch) -> list:
     rec["fp32s"]["error_vs_oracle_256x256"] = field_errors(
         host_moments(lb, torch), oracle.moments(oracle.run(oracle.init_feq(*fs), P, n)))
     del lb
-    out.append(rec)
+    torch.cuda.empty_cache()
     log("workloads: %s" % rec)
+    return rec
 
-    # adjoint: 512 x 512, 200 steps, gradient of KE w.r.t. 16 amplitudes, k = 20
+
+def _adjoint_workload(torch) -> dict:
+    """512 x 512, 200 steps: gradient of the final kinetic energy w.r.t. the 16
+    interface amplitudes (adjoint, checkpoints every 20) against central
+    finite differences, and its cost relative to the forward run."""
+    import numpy as np
+
+    from paper_1703_00186_amd import adjoint, workload
+    from paper_1703_00186_amd.lb import LB
+
     lx, ly, n, k = 512, 512, 200, 20
     seed = workload.config_seed(4)
     rho, ux, uy, T, info = workload.rt_fields(lx, ly, seed=seed, mode="multimode")
@@ -277,18 +305,24 @@ def run_workloads(args, torch) -> list:
             e[j] = h
             gfd[j] = (ke_of(info["amplitudes"] + e) - ke_of(info["amplitudes"] - e)) / (2 * h)
         fd["%g" % h] = float(np.abs(g - gfd).max() / np.abs(gfd).max())
-    out.append({"workload": "adjoint 512x512", "lattice": [lx, ly], "steps": n, "checkpoint_every": k,
-                "KE": float(ke.detach().cpu()), "max_abs_grad": float(np.abs(g).max()),
-                "adjoint_vs_central_fd": fd, "forward_s": round(t_plain, 5),
-                "forward_with_checkpoints_s": round(t1 - t0, 5), "backward_s": round(t2 - t1, 5),
-                "backward_over_forward": round((t2 - t1) / t_plain, 3)})
-    log("workloads: %s" % out[-1])
+    rec = {"workload": "adjoint 512x512", "lattice": [lx, ly], "steps": n, "checkpoint_every": k,
+           "KE": float(ke.detach().cpu()), "max_abs_grad": float(np.abs(g).max()),
+           "adjoint_vs_central_fd": fd, "forward_s": round(t_plain, 5),
+           "forward_with_checkpoints_s": round(t1 - t0, 5), "backward_s": round(t2 - t1, 5),
+           "backward_over_forward": round((t2 - t1) / t_plain, 3)}
+    log("workloads: %s" % rec)
     del lb, fields
     torch.cuda.empty_cache()
+    return rec
 
-    # production: 8192 x 4096, FP64 and FP32 shifted, then the adjoint of
-    # the last 100 FP64 steps (checkpoints every 20)
-    lx, ly, n, n_adj = 8192, 4096, args.c5_steps, 100
+
+def _production_workload(args, torch) -> dict:
+    """8192 x 4096: FP64 and FP32 shifted speed and footprint, then the
+    adjoint of the last 100 FP64 steps (checkpoints every 20)."""
+    from paper_1703_00186_amd import workload
+    from paper_1703_00186_amd.lb import LB
+
+    lx, ly, n, n_adj = 8192, 4096, args.production_steps, 100
     sites = lx * ly
     seed = workload.config_seed(5)
     rho, ux, uy, T, info = workload.rt_fields(lx, ly, seed=seed, mode="multimode")
@@ -338,9 +372,8 @@ def run_workloads(args, torch) -> list:
     rec["peak_device_GB"] = round(torch.cuda.max_memory_allocated() / 1e9, 2)
     del lb, ckpts, tape, spare, lam
     torch.cuda.empty_cache()
-    out.append(rec)
     log("workloads: %s" % rec)
-    return out
+    return rec
 
 
 def run_ablations(args, torch) -> list:
@@ -445,14 +478,17 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="time only the headline fused FP64 step (for profiling)")
-    ap.add_argument("--workloads", action="store_true",
-                    help="run the parity, FP32-precision, adjoint and production workloads "
-                         "and print one JSON record each instead of the headline line")
+    ap.add_argument("--workloads", nargs="*", default=None,
+                    choices=["parity", "fp32", "adjoint", "production"],
+                    help="run these workloads (all four when none is named) and print one "
+                         "JSON record each instead of the headline line")
     ap.add_argument("--ablations", action="store_true",
                     help="run the layout / collision / stability / FP32-shift ablations")
     ap.add_argument("--stability-steps", type=int, default=5000)
-    ap.add_argument("--c3-steps", type=int, default=2000)
-    ap.add_argument("--c5-steps", type=int, default=5000)
+    ap.add_argument("--fp32-steps", type=int, default=2000,
+                    help="steps of the 4096 x 4096 FP32-precision workload")
+    ap.add_argument("--production-steps", type=int, default=5000,
+                    help="steps of the 8192 x 4096 production workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scale reference)")
     args = ap.parse_args(argv)
@@ -468,8 +504,8 @@ def main(argv=None) -> int:
     from paper_1703_00186_amd import workload
     from paper_1703_00186_amd.lb import LB
 
-    if args.workloads or args.ablations:
-        for rec in (run_workloads if args.workloads else run_ablations)(args, torch):
+    if args.workloads is not None or args.ablations:
+        for rec in (run_workloads if args.workloads is not None else run_ablations)(args, torch):
             print(json.dumps(rec), flush=True)
         return 0
 
