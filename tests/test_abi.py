@@ -105,3 +105,11 @@ def test_bench_accounting_reproduces_table1():
     assert abs(gbs - vals["prop_gbs"]) < 0.5
     assert abs(bench.mlups(sites, vals["t_collide_ms"] * 1e-3) - vals["collide_mlups"]) < 0.5
     assert abs(bench.mlups(sites, vals["t_wc_ms"] * 1e-3) - vals["wc_mlups"]) < 0.5
+
+
+def test_binding_refuses_to_run_without_the_hip_library(monkeypatch, tmp_path):
+    """No CPU fallback: with the library missing, the binding raises."""
+    monkeypatch.setattr(lbmod, "_lib", None)
+    monkeypatch.setattr(lbmod, "library_path", lambda: str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        lbmod.load_library()

@@ -35,20 +35,21 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def setup(lx, ly, ybc="walls", regularize=1, g=(1e-3, -2e-3), steps=3, seed=5):
+def setup(lx, ly, ybc="walls", regularize=1, g=(1e-3, -2e-3), steps=3, seed=5, layout="column"):
     rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=seed)
     P = oracle.Params(tau=0.7, gx=g[0], gy=g[1], t_bottom=1.5, t_top=0.5,
                       regularize=regularize, ybc=1 if ybc == "periodic" else 0)
     f = oracle.run(oracle.init_feq(rho, ux, uy, T), P, steps)
-    lb = LB(lx, ly, rho, ux, uy, T, ybc=ybc, regularize=regularize, g=g)
+    lb = LB(lx, ly, rho, ux, uy, T, ybc=ybc, regularize=regularize, g=g, layout=layout)
     return lb, P, f, (rho, ux, uy, T)
 
 
-@pytest.mark.parametrize("ybc", ["walls", "periodic"])
-@pytest.mark.parametrize("regularize", [1, 0])
-def test_step_transpose(ybc, regularize):
+@pytest.mark.parametrize("ybc,regularize,layout", [
+    ("walls", 1, "column"), ("walls", 0, "column"), ("periodic", 1, "column"),
+    ("periodic", 0, "column"), ("walls", 1, "soa"), ("periodic", 0, "soa")])
+def test_step_transpose(ybc, regularize, layout):
     lx, ly = 24, 20
-    lb, P, f, _ = setup(lx, ly, ybc, regularize)
+    lb, P, f, _ = setup(lx, ly, ybc, regularize, layout=layout)
     lb.set_state(torch.from_numpy(f))
     tape = lb.new_tape(1)
     lb.step_record(1, tape)

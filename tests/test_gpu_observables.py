@@ -30,12 +30,13 @@ def reference(f, t_bottom, t_top):
     return prof, sc
 
 
+@pytest.mark.parametrize("layout", ["column", "soa"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32s"])
 @pytest.mark.parametrize("shape", [(96, 200), (70, 33), (256, 128)])
-def test_observables_match_oracle_moments(precision, shape):
+def test_observables_match_oracle_moments(precision, shape, layout):
     lx, ly = shape
     f = workload.rt_fields(lx, ly, seed=3)[:4]
-    lb = LB(lx, ly, *f, precision=precision)
+    lb = LB(lx, ly, *f, precision=precision, layout=layout)
     lb.step(30)
     prof, sc = lb.observables()
     torch.cuda.synchronize()
