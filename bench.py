@@ -260,7 +260,8 @@ def _fp32_workload(args, P, torch) -> dict:
 def _adjoint_workload(torch) -> dict:
     """512 x 512, 200 steps: gradient of the final kinetic energy w.r.t. the 16
     interface amplitudes (adjoint, checkpoints every 20) against central
-    finite differences, and its cost relative to the forward run."""
+    finite differences, and its cost relative to the forward run; then the
+    same gradient from a full tape (no recomputation)."""
     import numpy as np
 
     from paper_1703_00186_amd import adjoint, workload
@@ -305,11 +306,30 @@ def _adjoint_workload(torch) -> dict:
             e[j] = h
             gfd[j] = (ke_of(info["amplitudes"] + e) - ke_of(info["amplitudes"] - e)) / (2 * h)
         fd["%g" % h] = float(np.abs(g - gfd).max() / np.abs(gfd).max())
+    # full tape: the forward run records the moments of all n steps, the
+    # backward run only applies the transposed steps
+    fields = [torch.from_numpy(a).cuda().requires_grad_(True) for a in (rho, ux, uy, T)]
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    ke_t = adjoint.kinetic_energy(lb, *fields, nsteps=n, checkpoint_every=0)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    ke_t.backward()
+    torch.cuda.synchronize()
+    t6 = time.perf_counter()
+    g_t = workload.amplitude_gradient(lx, ly, fields[0].grad.cpu().numpy(),
+                                      fields[3].grad.cpu().numpy(), seed=seed)
     rec = {"workload": "adjoint 512x512", "lattice": [lx, ly], "steps": n, "checkpoint_every": k,
            "KE": float(ke.detach().cpu()), "max_abs_grad": float(np.abs(g).max()),
            "adjoint_vs_central_fd": fd, "forward_s": round(t_plain, 5),
            "forward_with_checkpoints_s": round(t1 - t0, 5), "backward_s": round(t2 - t1, 5),
-           "backward_over_forward": round((t2 - t1) / t_plain, 3)}
+           "backward_over_forward": round((t2 - t1) / t_plain, 3),
+           "full_tape": {"tape_GB": round(n * 4 * lx * ly * 8 / 1e9, 3),
+                         "forward_recording_s": round(t5 - t4, 5),
+                         "backward_s": round(t6 - t5, 5),
+                         "backward_over_forward": round((t6 - t5) / t_plain, 3),
+                         "gradient_vs_checkpointed": float(np.abs(g_t - g).max() /
+                                                           np.abs(g).max())}}
     log("workloads: %s" % rec)
     del lb, fields
     torch.cuda.empty_cache()
@@ -318,7 +338,8 @@ def _adjoint_workload(torch) -> dict:
 
 def _production_workload(args, torch) -> dict:
     """8192 x 4096: FP64 and FP32 shifted speed and footprint, then the
-    adjoint of the last 100 FP64 steps (checkpoints every 20)."""
+    adjoint of the last 100 FP64 steps, with checkpoints every 20 steps and
+    with a full tape."""
     from paper_1703_00186_amd import workload
     from paper_1703_00186_amd.lb import LB
 
@@ -354,7 +375,7 @@ def _production_workload(args, torch) -> dict:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     tape = lb.new_tape(k)
-    spare = lb.new_populations(torch.float64)
+    spare = lb.new_lambda()
     for ck in reversed(ckpts):
         lb.set_state(ck)
         lb.step_record(k, tape)
@@ -369,8 +390,36 @@ def _production_workload(args, torch) -> dict:
         "backward_s": round(t2 - t1, 4), "backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
         "checkpoints_tape_lambda_GB": round(extra / 1e9, 3),
         "lambda_norm": float(lam.norm().cpu())}
+    # the same gradient from a full tape of the n_adj steps (32 B per site and
+    # step) instead of checkpoints and recomputation
+    ck0, lam_ckpt = ckpts[0], lam
+    del ckpts, tape, spare
+    torch.cuda.empty_cache()
+    base = device_bytes_in_use(torch)
+    lb.set_state(ck0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tape = lb.new_tape(n_adj)
+    lb.step_record(n_adj, tape)
+    ke, lam = lb.loss_ke(with_lambda=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    spare = lb.new_lambda()
+    for j in range(n_adj - 1, -1, -1):
+        lb.adjoint_step(tape[j], lam, spare)
+        lam, spare = spare, lam
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    extra = device_bytes_in_use(torch) - base
+    rec["fp64"]["adjoint_last_steps_full_tape"] = {
+        "steps": n_adj, "forward_recording_s": round(t1 - t0, 4),
+        "backward_s": round(t2 - t1, 4),
+        "backward_over_forward": round((t2 - t1) / rec["fp64"]["adjoint_last_steps"]["forward_s"],
+                                       3),
+        "tape_lambda_GB": round(extra / 1e9, 3),
+        "lambda_vs_checkpointed": float((lam - lam_ckpt).norm().cpu() / lam_ckpt.norm().cpu())}
     rec["peak_device_GB"] = round(torch.cuda.max_memory_allocated() / 1e9, 2)
-    del lb, ckpts, tape, spare, lam
+    del lb, ck0, tape, spare, lam, lam_ckpt
     torch.cuda.empty_cache()
     log("workloads: %s" % rec)
     return rec

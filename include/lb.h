@@ -178,14 +178,19 @@ int lb_run_observed(lb_ctx* ctx, int n, int every, double* series);
  * each step j, the four pre-collision moments m = (rho, rho u_x, rho u_y,
  * sum |c|^2 f) of every site to tape + j*4*lx*ly as [4][lx][ly] FP64.
  *
+ * Adjoint populations (lambda, 37 * lx * ly FP64 values, no halos) are laid
+ * out like the context's populations: [lx][37][ly] for LB_LAYOUT_COLUMN,
+ * [37][lx][ly] for LB_LAYOUT_SOA (y contiguous in both).
+ *
  * lb_loss_ke: KE = (1/2) sum rho |u|^2 of the current state into ke_dev (one
  * device double) and, if lambda != NULL, dKE/df_l = c_l.u - |u|^2/2 into
- * lambda [37][lx][ly].
+ * lambda.
  *
  * lb_adjoint_step: lambda_out = (d f^{n+1} / d f^n)^T lambda_in for the step
  * whose pre-collision moments are tape_j ([4][lx][ly] from lb_step_record):
  * the transposed collision, walls and propagation, in one kernel.  lambda_in
- * and lambda_out are distinct [37][lx][ly] buffers.
+ * and lambda_out are distinct buffers; every element of lambda_out is
+ * written.
  *
  * lb_init_adjoint: given lambda0 = dL/df^0 and the initial fields
  * (rho0, ux0, uy0, T0) the state was built from, writes dL/d(rho0, ux0, uy0,

@@ -330,10 +330,10 @@ __global__ __launch_bounds__(kThreads) void k_loss_ke(const double* __restrict__
     const double u2 = m.ux * m.ux + m.uy * m.uy;
     ke = 0.5 * m.rho * u2;
     if (lambda) {
-      const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
+      const long long s = (long long)x * g.lcs + y;
 #pragma unroll
       for (int l = 0; l < Q; ++l)
-        lambda[l * S2 + s] = R * (EX[l] * m.ux + EY[l] * m.uy) - 0.5 * u2;
+        lambda[l * g.lps + s] = R * (EX[l] * m.ux + EY[l] * m.uy) - 0.5 * u2;
     }
   }
   const double tot = block_sum(ke);
@@ -398,10 +398,12 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const double* __restrict__
                                                       unsigned nb) {
   int x, y;
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  // tape: [4][lx][ly]; lambda: compact, in the lattice's layout
   const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
+  const long long sl = (long long)x * g.lcs + y;
   double lam[Q];
 #pragma unroll
-  for (int l = 0; l < Q; ++l) lam[l] = lam_in[l * S2 + s];
+  for (int l = 0; l < Q; ++l) lam[l] = lam_in[l * g.lps + sl];
   const double rho = tape[s], jx = tape[S2 + s], jy = tape[2 * S2 + s], e = tape[3 * S2 + s];
   const double inv = 1.0 / rho;
   const double ux = jx * inv, uy = jy * inv;
@@ -470,14 +472,14 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const double* __restrict__
     xs += xs < 0 ? g.lx : (xs >= g.lx ? -g.lx : 0);
     int yd = ys;
     if (!g.walls) yd += yd < 0 ? g.ly : (yd >= g.ly ? -g.ly : 0);
-    lam_out[l * S2 + (long long)xs * g.ly + yd] = mu[l];
+    lam_out[l * g.lps + (long long)xs * g.lcs + yd] = mu[l];
   }
   // Populations leaving through a wall from this site reach no site: zero.
   if (on_wall_rows(g, y)) {
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
       const int yd = y + EY[l];
-      if (yd < 0 || yd >= g.ly) lam_out[l * S2 + s] = 0.0;
+      if (yd < 0 || yd >= g.ly) lam_out[l * g.lps + sl] = 0.0;
     }
   }
 }
@@ -489,10 +491,10 @@ __global__ __launch_bounds__(kThreads) void k_init_adjoint(
     double* __restrict__ dT, Geom g, int by, int bx, int nty, unsigned nb) {
   int x, y;
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
-  const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
+  const long long s = (long long)x * g.ly + y, sl = (long long)x * g.lcs + y;
   double lam[Q];
 #pragma unroll
-  for (int l = 0; l < Q; ++l) lam[l] = lam0[l * S2 + s];
+  for (int l = 0; l < Q; ++l) lam[l] = lam0[l * g.lps + sl];
   double L[5][5];
   adjoint_project(lam, L);
   const EqGrad G = equilibrium_grad(L, rho[s], ux[s], uy[s], T[s] - 1.0);

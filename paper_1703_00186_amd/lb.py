@@ -148,6 +148,7 @@ class LB:
         self.device = torch.device(device)
         self.lx, self.ly = int(lx), int(ly)
         self.precision = precision
+        self.layout = layout
         self.lat = make_lattice(lx, ly, precision, ybc, layout)
         self.params = dict(params)
         self.par = make_params(**self.params)
@@ -183,6 +184,32 @@ class LB:
     def new_populations(self, dtype=None) -> torch.Tensor:
         return torch.empty((Q, self.lx, self.ly), dtype=dtype or self.state_dtype,
                            device=self.device)
+
+    # adjoint populations are stored in the lattice's layout: [lx, 37, ly]
+    # (column) or [37, lx, ly] (SoA); lambda_view gives the [37, lx, ly] view
+    @property
+    def lambda_shape(self):
+        return (self.lx, Q, self.ly) if self.layout == "column" else (Q, self.lx, self.ly)
+
+    def new_lambda(self) -> torch.Tensor:
+        return torch.empty(self.lambda_shape, dtype=torch.float64, device=self.device)
+
+    def lambda_view(self, lam: torch.Tensor) -> torch.Tensor:
+        """[37, lx, ly] view of an adjoint array (no copy)."""
+        self._check_lambda(lam)
+        return lam.permute(1, 0, 2) if self.layout == "column" else lam
+
+    def lambda_from(self, lam_std) -> torch.Tensor:
+        """Copy of a [37, lx, ly] array in the adjoint layout, on the device."""
+        t = torch.as_tensor(lam_std, dtype=torch.float64).to(self.device)
+        if tuple(t.shape) != (Q, self.lx, self.ly):
+            raise ValueError("expected [37, lx, ly]")
+        return (t.permute(1, 0, 2) if self.layout == "column" else t).contiguous()
+
+    def _check_lambda(self, lam: torch.Tensor):
+        if (tuple(lam.shape) != self.lambda_shape or lam.dtype != torch.float64
+                or not lam.is_contiguous()):
+            raise ValueError("adjoint array must be contiguous float64 %s" % (self.lambda_shape,))
 
     # -- the step ------------------------------------------------------------
     def set_params(self, **params):
@@ -309,15 +336,18 @@ class LB:
     def loss_ke(self, with_lambda: bool = True):
         self._sync_stream()
         ke = torch.empty(1, dtype=torch.float64, device=self.device)
-        lam = self.new_populations(torch.float64) if with_lambda else None
+        lam = self.new_lambda() if with_lambda else None
         _check(self.lib.lb_loss_ke(self.ctx, _ptr(ke), _ptr(lam)))
         return ke, lam
 
     def adjoint_step(self, tape_j: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor):
+        self._check_lambda(lam_in)
+        self._check_lambda(lam_out)
         self._sync_stream()
         _check(self.lib.lb_adjoint_step(self.ctx, _ptr(tape_j), _ptr(lam_in), _ptr(lam_out)))
 
     def init_adjoint(self, rho0, ux0, uy0, T0, lam0: torch.Tensor):
+        self._check_lambda(lam0)
         self._sync_stream()
         fields = [self.field(a) for a in (rho0, ux0, uy0, T0)]
         out = [torch.empty((self.lx, self.ly), dtype=torch.float64, device=self.device)

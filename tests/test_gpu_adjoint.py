@@ -60,9 +60,9 @@ def test_step_transpose(ybc, regularize, layout):
         if trial == 1:  # weight the wall rows
             lam[:, :, 3:-3] *= 1e-3
             v[:, :, 3:-3] *= 1e-3
-        out = torch.empty((37, lx, ly), dtype=torch.float64, device="cuda")
-        lb.adjoint_step(tape[0], torch.from_numpy(lam).cuda(), out)
-        jt_lam = host(out)
+        out = lb.new_lambda()
+        lb.adjoint_step(tape[0], lb.lambda_from(lam), out)
+        jt_lam = host(lb.lambda_view(out))
         jv = oracle.run_complex(f + 1j * H * v, P, 1).imag / H
         a, b = np.sum(jv * lam), np.sum(v * jt_lam)
         assert abs(a - b) <= 1e-12 * (np.abs(jv * lam).sum()), (a, b)
@@ -82,15 +82,16 @@ def test_tape_holds_pre_collision_moments():
     assert np.allclose(host(tape[0]), ref, rtol=1e-14, atol=1e-14)
 
 
-def test_init_transpose():
+@pytest.mark.parametrize("layout", ["column", "soa"])
+def test_init_transpose(layout):
     lx, ly = 20, 16
     rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=9)
     ux = ux + 0.01
     uy = uy - 0.02
-    lb = LB(lx, ly, rho, ux, uy, T)
+    lb = LB(lx, ly, rho, ux, uy, T, layout=layout)
     rng = np.random.default_rng(3)
     lam = rng.standard_normal((37, lx, ly))
-    d = [host(t) for t in lb.init_adjoint(rho, ux, uy, T, torch.from_numpy(lam).cuda())]
+    d = [host(t) for t in lb.init_adjoint(rho, ux, uy, T, lb.lambda_from(lam))]
     dv = [rng.standard_normal((lx, ly)) for _ in range(4)]
     fc = oracle.init_feq_complex(*[a + 1j * H * b for a, b in zip((rho, ux, uy, T), dv)])
     a = np.sum(fc.imag / H * lam)
@@ -98,15 +99,17 @@ def test_init_transpose():
     assert abs(a - b) <= 1e-12 * np.abs(fc.imag / H * lam).sum()
 
 
-def test_loss_gradient():
+@pytest.mark.parametrize("layout", ["column", "soa"])
+def test_loss_gradient(layout):
     lx, ly = 20, 16
-    lb, P, f, _ = setup(lx, ly)
+    lb, P, f, _ = setup(lx, ly, layout=layout)
     lb.set_state(torch.from_numpy(f))
     ke, lam = lb.loss_ke(with_lambda=True)
     assert abs(host(ke)[0] - oracle.kinetic_energy(f)) <= 1e-13 * oracle.kinetic_energy(f)
     v = np.random.default_rng(1).standard_normal((37, lx, ly))
     d = oracle.kinetic_energy_complex(f + 1j * H * v).imag / H
-    assert abs(np.sum(host(lam) * v) - d) <= 1e-12 * np.abs(host(lam) * v).sum()
+    lam = host(lb.lambda_view(lam))
+    assert abs(np.sum(lam * v) - d) <= 1e-12 * np.abs(lam * v).sum()
 
 
 def amplitude_grad_gpu(lb, lx, ly, seed, nsteps, every):
@@ -126,8 +129,10 @@ def amplitude_grad_gpu(lb, lx, ly, seed, nsteps, every):
     return float(ke.detach().cpu()), grad, t1 - t0, t2 - t1
 
 
-def test_gradient_matches_oracle_complex_step_64():
-    lx, ly, nsteps, every = 64, 64, 200, 20
+@pytest.mark.parametrize("every", [20, 0])
+def test_gradient_matches_oracle_complex_step_64(every):
+    """Checkpoints every 20 steps, and the full tape (every = 0)."""
+    lx, ly, nsteps = 64, 64, 200
     seed = workload.config_seed(4)
     rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=seed, mode="multimode")
     lb = LB(lx, ly, rho, ux, uy, T)
@@ -142,6 +147,47 @@ def test_gradient_matches_oracle_complex_step_64():
         g_cs[k] = oracle.ke_after_steps_complex(P, *f, nsteps).imag / H
     err = np.abs(g_gpu - g_cs).max() / np.abs(g_cs).max()
     assert err <= 1e-10, (err, g_gpu, g_cs)
+
+
+@pytest.mark.parametrize("nsteps", [0, 1, 37])
+def test_full_tape_equals_checkpointed(nsteps):
+    """Both modes apply the same transposed steps to the same recorded
+    moments; checkpoint intervals that do not divide the run included."""
+    lx, ly = 48, 40
+    rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=8, mode="multimode")
+    lb = LB(lx, ly, rho, ux, uy, T)
+    grads = []
+    for every in (0, 5, 64):
+        fields = [torch.from_numpy(a).cuda().requires_grad_(True) for a in (rho, ux, uy, T)]
+        adjoint.kinetic_energy(lb, *fields, nsteps=nsteps, checkpoint_every=every).backward()
+        grads.append(np.stack([host(f.grad) for f in fields]))
+    scale = np.abs(grads[0]).max()
+    for g in grads[1:]:
+        assert np.abs(g - grads[0]).max() <= 1e-13 * scale
+
+
+def test_full_tape_cost():
+    """Without recomputation the backward pass is one adjoint launch per
+    step: at most 1.5 forward runs (624 against 592 bytes per site)."""
+    lx, ly, nsteps = 512, 512, 200
+    seed = workload.config_seed(4)
+    rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=seed, mode="multimode")
+    lb = LB(lx, ly, rho, ux, uy, T)
+    amplitude_grad_gpu(lb, lx, ly, seed, 40, 0)  # warm-up
+    _, g_tape, t_fwd_tape, t_bwd = amplitude_grad_gpu(lb, lx, ly, seed, nsteps, 0)
+    _, g_ckpt, _, _ = amplitude_grad_gpu(lb, lx, ly, seed, nsteps, 20)
+    assert np.abs(g_tape - g_ckpt).max() <= 1e-12 * np.abs(g_ckpt).max()
+    fields = [lb.field(a) for a in (rho, ux, uy, T)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lb.reinit(*fields)
+    lb.step(nsteps)
+    lb.loss_ke(with_lambda=False)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    print("full tape 512x512x200: forward %.4f s (recording %.4f s), backward %.4f s, ratio %.2f"
+          % (t_fwd, t_fwd_tape, t_bwd, t_bwd / t_fwd))
+    assert t_bwd <= 1.5 * t_fwd, (t_bwd, t_fwd)
 
 
 def test_gradient_512_vs_finite_differences_and_cost():
