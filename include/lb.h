@@ -23,7 +23,9 @@
  *    The caller owns ALL device memory, including the workspace; the library
  *    owns only the host-side lb_ctx (freed by lb_free).
  *  - Fields (rho, ux, uy, T, gradients) are FP64, x-major [lx][ly], contiguous
- *    (y fastest).  Population arrays in the compact form are [37][lx][ly].
+ *    (y fastest).  Population arrays in the compact form (lb_get_state and
+ *    the like) are [37][lx][ly]; adjoint arrays follow the lattice's layout
+ *    (see the adjoint section).
  *  - Work is enqueued asynchronously on the stream given to lb_init (a
  *    hipStream_t passed as void*, NULL = the null stream); nothing waits for
  *    the GPU except lb_step with check_finite > 0.  The caller synchronises
@@ -92,6 +94,7 @@ typedef struct lb_params {
 typedef struct lb_ctx lb_ctx;
 
 const char* lb_last_error(void);
+/* Interface version: 2 (adjoint arrays in the lattice's layout). */
 int lb_version(void);
 
 /* Bytes of device workspace lb_init needs for this lattice (two padded

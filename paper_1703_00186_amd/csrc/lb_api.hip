@@ -208,7 +208,7 @@ extern "C" {
 
 const char* lb_last_error(void) { return g_error.c_str(); }
 
-int lb_version(void) { return 1; }
+int lb_version(void) { return 2; }
 
 int lb_workspace_bytes(const lb_lattice* lat, const lb_params* par, size_t* bytes) {
   int rc = check_lattice(lat);

@@ -107,6 +107,10 @@ def test_bench_accounting_reproduces_table1():
     assert abs(bench.mlups(sites, vals["t_wc_ms"] * 1e-3) - vals["wc_mlups"]) < 0.5
 
 
+def test_version(lib):
+    assert lib.lb_version() == 2
+
+
 def test_binding_refuses_to_run_without_the_hip_library(monkeypatch, tmp_path):
     """No CPU fallback: with the library missing, the binding raises."""
     monkeypatch.setattr(lbmod, "_lib", None)
