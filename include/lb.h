@@ -70,8 +70,9 @@ extern "C" {
 #define LB_KERNEL_SPLIT 1 /* halo, propagate, bc, collide as separate kernels */
 
 typedef struct lb_lattice {
-  int32_t lx;        /* physical sites along x (periodic), >= 6         */
-  int32_t ly;        /* physical sites along y (walls), >= 6            */
+  int32_t lx;        /* physical sites along x (periodic), 6 .. 2^22    */
+  int32_t ly;        /* physical sites along y (walls), 6 .. 2^24;      */
+                     /* lx * ly <= 2^30                                 */
   int32_t precision; /* LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM */
   int32_t ybc;       /* LB_Y_WALLS or LB_Y_PERIODIC                     */
   int32_t layout;    /* LB_LAYOUT_SOA or LB_LAYOUT_COLUMN               */

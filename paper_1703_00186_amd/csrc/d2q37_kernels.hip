@@ -9,6 +9,8 @@
 // neighbouring row tile of the same column, which then hits that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "d2q37_launch.h"
 
 namespace d2q37 {
@@ -256,48 +258,60 @@ __global__ __launch_bounds__(kThreads) void k_check(const S* __restrict__ src,
   if (bad) atomicAdd(flag, 1u);
 }
 
-// compact [37][lx][ly] <-> padded
+// compact [37][lx][ly] <-> padded.  One workgroup copies up to kThreads
+// consecutive y of one (population, column) row: population blockIdx.y,
+// column and y block from blockIdx.x with scalar arithmetic (no per-lane
+// 64-bit division).
+struct CompactSite {
+  long long compact, padded;
+  bool in;
+  int l;
+};
+
+__device__ __forceinline__ CompactSite compact_site(const Geom& g, unsigned nyb) {
+  const unsigned x = blockIdx.x / nyb, yb = blockIdx.x - x * nyb;
+  const int l = int(blockIdx.y);
+  const int y = int(yb) * kThreads + int(threadIdx.x);
+  CompactSite c;
+  c.in = y < g.ly;
+  c.l = l;
+  c.compact = ((long long)l * g.lx + x) * g.ly + y;
+  c.padded = l * g.ps + (long long)(x + HX) * g.cs + (y + g.hy);
+  return c;
+}
+
 template <class S>
 __global__ __launch_bounds__(kThreads) void k_pack(const S* __restrict__ padded_buf,
-                                                   S* __restrict__ compact, Geom g) {
-  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
-  const long long S2 = (long long)g.lx * g.ly;
-  if (i >= S2 * Q) return;
-  const int l = int(i / S2);
-  const int x = int((i % S2) / g.ly), y = int(i % g.ly);
-  compact[i] = padded_buf[l * g.ps + (long long)(x + HX) * g.cs + (y + g.hy)];
+                                                   S* __restrict__ compact, Geom g,
+                                                   unsigned nyb) {
+  const CompactSite c = compact_site(g, nyb);
+  if (c.in) __builtin_nontemporal_store(padded_buf[c.padded], &compact[c.compact]);
 }
 
 template <class S>
 __global__ __launch_bounds__(kThreads) void k_unpack(const S* __restrict__ compact,
-                                                     S* __restrict__ padded_buf, Geom g) {
-  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
-  const long long S2 = (long long)g.lx * g.ly;
-  if (i >= S2 * Q) return;
-  const int l = int(i / S2);
-  const int x = int((i % S2) / g.ly), y = int(i % g.ly);
-  padded_buf[l * g.ps + (long long)(x + HX) * g.cs + (y + g.hy)] = compact[i];
+                                                     S* __restrict__ padded_buf, Geom g,
+                                                     unsigned nyb) {
+  const CompactSite c = compact_site(g, nyb);
+  if (c.in) __builtin_nontemporal_store(compact[c.compact], &padded_buf[c.padded]);
 }
 
 template <class S>
 __global__ __launch_bounds__(kThreads) void k_populations_f64(const S* __restrict__ padded_buf,
                                                               double* __restrict__ out, Geom g,
-                                                              double rho_ref) {
-  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
-  const long long S2 = (long long)g.lx * g.ly;
-  if (i >= S2 * Q) return;
-  const int l = int(i / S2);
-  const int x = int((i % S2) / g.ly), y = int(i % g.ly);
+                                                              double rho_ref, unsigned nyb) {
+  const CompactSite c = compact_site(g, nyb);
+  if (!c.in) return;
   double w = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k)
-    if (k == l) w = W[k];
-  out[i] = double(padded_buf[l * g.ps + (long long)(x + HX) * g.cs + (y + g.hy)]) + rho_ref * w;
+    if (k == c.l) w = W[k];
+  out[c.compact] = double(padded_buf[c.padded]) + rho_ref * w;
 }
 
 __global__ __launch_bounds__(kThreads) void k_zero(unsigned int* __restrict__ p, long long n) {
-  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
-  if (i < n) p[i] = 0u;
+  const long long stride = (long long)gridDim.x * kThreads;
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -607,7 +621,8 @@ hipError_t by_precision(int prec, Fn fn) {
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   const long long n = (long long)(bytes / 4);
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero, dim3(grid_1d(n)), dim3(kThreads), 0, s,
+  const unsigned grid = std::min(grid_1d(n), 1u << 20);  // grid-stride beyond 2^28 words
+  hipLaunchKernelGGL(k_zero, dim3(grid), dim3(kThreads), 0, s,
                      static_cast<unsigned int*>(p), n);
   return hipGetLastError();
 }
@@ -708,33 +723,45 @@ hipError_t launch_moments(const void* src, double* rho, double* ux, double* uy, 
   });
 }
 
+// workgroups of the compact copies: lx columns of ceil(ly / kThreads) blocks
+// along x, the 37 populations along y
+struct CompactGrid {
+  dim3 grid;
+  unsigned nyb;
+};
+
+CompactGrid compact_grid(const Geom& g) {
+  const unsigned nyb = unsigned((g.ly + kThreads - 1) / kThreads);
+  return {dim3(unsigned(g.lx) * nyb, Q), nyb};
+}
+
 hipError_t launch_pack(const void* padded_buf, void* compact, const Geom& g, int prec,
                        hipStream_t s) {
-  const unsigned grid = grid_1d((long long)g.lx * g.ly * Q);
+  const CompactGrid cg = compact_grid(g);
   return by_precision(prec, [&](auto sv, auto) {
     using S = decltype(sv);
-    hipLaunchKernelGGL(k_pack<S>, dim3(grid), dim3(kThreads), 0, s,
-                       static_cast<const S*>(padded_buf), static_cast<S*>(compact), g);
+    hipLaunchKernelGGL(k_pack<S>, cg.grid, dim3(kThreads), 0, s,
+                       static_cast<const S*>(padded_buf), static_cast<S*>(compact), g, cg.nyb);
   });
 }
 
 hipError_t launch_unpack(const void* compact, void* padded_buf, const Geom& g, int prec,
                          hipStream_t s) {
-  const unsigned grid = grid_1d((long long)g.lx * g.ly * Q);
+  const CompactGrid cg = compact_grid(g);
   return by_precision(prec, [&](auto sv, auto) {
     using S = decltype(sv);
-    hipLaunchKernelGGL(k_unpack<S>, dim3(grid), dim3(kThreads), 0, s,
-                       static_cast<const S*>(compact), static_cast<S*>(padded_buf), g);
+    hipLaunchKernelGGL(k_unpack<S>, cg.grid, dim3(kThreads), 0, s,
+                       static_cast<const S*>(compact), static_cast<S*>(padded_buf), g, cg.nyb);
   });
 }
 
 hipError_t launch_populations_f64(const void* padded_buf, double* out, const Geom& g,
                                   const Phys& p, int prec, hipStream_t s) {
-  const unsigned grid = grid_1d((long long)g.lx * g.ly * Q);
+  const CompactGrid cg = compact_grid(g);
   return by_precision(prec, [&](auto sv, auto) {
     using S = decltype(sv);
-    hipLaunchKernelGGL(k_populations_f64<S>, dim3(grid), dim3(kThreads), 0, s,
-                       static_cast<const S*>(padded_buf), out, g, p.rho_ref);
+    hipLaunchKernelGGL(k_populations_f64<S>, cg.grid, dim3(kThreads), 0, s,
+                       static_cast<const S*>(padded_buf), out, g, p.rho_ref, cg.nyb);
   });
 }
 

@@ -63,7 +63,11 @@ int elem_bytes(int prec) { return prec == LB_FP64 ? 8 : 4; }
 int check_lattice(const lb_lattice* lat) {
   if (!lat) return fail(LB_E_ARG, "lattice is NULL%s");
   if (lat->lx < 6 || lat->ly < 6) return fail(LB_E_ARG, "lx and ly must be >= 6%s");
-  if (lat->lx > (1 << 24) || lat->ly > (1 << 24)) return fail(LB_E_ARG, "lattice too large%s");
+  // bounds that keep every launch below 2^32 work-items (tile grids cover at
+  // most lx*ly + 256*lx + 4*ly + 256 sites) and all 32-bit site indices exact
+  if (lat->lx > (1 << 22) || lat->ly > (1 << 24) ||
+      (long long)lat->lx * lat->ly > (1LL << 30))
+    return fail(LB_E_ARG, "lattice too large (lx <= 2^22, ly <= 2^24, lx*ly <= 2^30)%s");
   if (lat->precision != LB_FP64 && lat->precision != LB_FP32_SHIFTED &&
       lat->precision != LB_FP32_SHIFTED_F32SUM)
     return fail(LB_E_ARG, "unknown precision%s");

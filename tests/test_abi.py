@@ -52,7 +52,8 @@ def test_workspace_bytes(lib):
 
 
 @pytest.mark.parametrize("bad", [dict(lx=5), dict(ly=3), dict(precision=7), dict(ybc=2),
-                                 dict(layout=9), dict(reserved=1)])
+                                 dict(layout=9), dict(reserved=1), dict(lx=(1 << 22) + 1),
+                                 dict(ly=(1 << 24) + 1), dict(lx=1 << 16, ly=(1 << 14) + 1)])
 def test_lattice_validation(lib, bad):
     lat = lbmod.make_lattice(64, 64)
     for k, v in bad.items():
@@ -105,6 +106,14 @@ def test_bench_accounting_reproduces_table1():
     assert abs(gbs - vals["prop_gbs"]) < 0.5
     assert abs(bench.mlups(sites, vals["t_collide_ms"] * 1e-3) - vals["collide_mlups"]) < 0.5
     assert abs(bench.mlups(sites, vals["t_wc_ms"] * 1e-3) - vals["wc_mlups"]) < 0.5
+
+
+def test_largest_lattice_is_accepted(lib):
+    lat = lbmod.make_lattice(1 << 16, 1 << 14)
+    n = ctypes.c_size_t(0)
+    assert lib.lb_workspace_bytes(ctypes.byref(lat), ctypes.byref(lbmod.make_params()),
+                                  ctypes.byref(n)) == 0
+    assert n.value > 2 * 37 * 8 * (1 << 30)
 
 
 def test_version(lib):
