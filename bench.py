@@ -40,7 +40,9 @@ def mlups(sites: int, seconds: float) -> float:
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_SUMMARY = os.path.join(PROFILES, "k_fused_fp64_rt1920x2048_hbm_traffic.md")
 VALU_SUMMARY = os.path.join(PROFILES, "k_fused_fp64_rt1920x2048_valu.md")
+FP32_VALU_SUMMARY = os.path.join(PROFILES, "k_fused_fp32_rt4096x4096_valu.md")
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 KERNEL_SOURCES = ["paper_1703_00186_amd/csrc/d2q37_kernels.hip",
                   "paper_1703_00186_amd/csrc/d2q37_device.h",
                   "paper_1703_00186_amd/csrc/d2q37_constants.h"]
@@ -86,6 +88,16 @@ def counted_flop_per_site():
     """FP64 flop per site counted by the VALU counters (None if stale)."""
     try:
         return float(summary_values(VALU_SUMMARY)["flop_per_site"])
+    except (KeyError, ValueError):
+        return None
+
+
+def counted_fp32_mode_flops(prec: str):
+    """(FP64, FP32) flop per site of the FP32-storage step `prec` from the
+    committed VALU counter summary, or None if missing or stale."""
+    vals = summary_values(FP32_VALU_SUMMARY)
+    try:
+        return float(vals[prec + "_flop64_per_site"]), float(vals[prec + "_flop32_per_site"])
     except (KeyError, ValueError):
         return None
 
@@ -624,6 +636,15 @@ def main(argv=None) -> int:
                 "GB/s": round(bytes_per_site("fp32") * sites / (t32 / args.steps) / 1e9, 1),
                 "error_vs_fp64_gpu": {k: float("%.3g" % v) for k, v in errs.items()},
                 "error_after_steps": args.warmup + args.steps}
+            fl = counted_fp32_mode_flops(prec)
+            if fl is not None:
+                rate = sites / (t32 / args.steps) / 1e12
+                out[key]["compute"] = {
+                    "fp64_flop_per_site_counted": fl[0], "fp32_flop_per_site_counted": fl[1],
+                    "fp64_TFLOPs": round(fl[0] * rate, 2),
+                    "fp64_frac": round(fl[0] * rate / FP64_VECTOR_PEAK_TFLOPS, 4),
+                    "fp32_TFLOPs": round(fl[1] * rate, 2),
+                    "fp32_frac": round(fl[1] * rate / FP32_VECTOR_PEAK_TFLOPS, 4)}
             log("bench: fused %s %.1f MLUPS (x%.2f), errors %s" % (prec, v32, v32 / value, errs))
             del lb32
             torch.cuda.empty_cache()
