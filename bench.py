@@ -180,18 +180,20 @@ def cpu_baseline(lx: int, ly: int, fields, steps: int) -> dict:
     t0 = time.perf_counter()
     oracle.run(f, P, steps)
     dt = time.perf_counter() - t0
-    cpu = "unknown"
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
     return {"value": round(mlups(lx * ly * steps, dt), 4), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": "%d steps of the %dx%d FP64 RT lattice after 1 warm-up step (%.1f s), %s"
-                      % (steps, lx, ly, dt, cpu)}
+                      % (steps, lx, ly, dt, cpu_model())}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 def device_bytes_in_use(torch) -> int:
@@ -506,7 +508,7 @@ def run_ablations(args, torch) -> list:
     return out
 
 
-def cpu_optimised(lx: int, ly: int, fields, steps: int = 10) -> dict:
+def cpu_optimised(lx: int, ly: int, fields, steps: int = 40) -> dict:
     """The vectorised multicore CPU implementation of the same step (a
     stronger CPU comparison than the oracle), on this host's cores."""
     import cpu_step
@@ -515,15 +517,15 @@ def cpu_optimised(lx: int, ly: int, fields, steps: int = 10) -> dict:
     threads = min(16, len(os.sched_getaffinity(0)))
     cpu_step.set_threads(threads)
     lat = cpu_step.CpuLattice(lx, ly, oracle.init_feq(*fields))
-    lat.step(1)
+    lat.step(2)
     t0 = time.perf_counter()
     lat.step(steps)
     dt = time.perf_counter() - t0
     return {"value": round(mlups(lx * ly * steps, dt), 2), "unit": "MLUPS", "cores": threads,
             "kind": "optimised CPU step (AVX-512)" if cpu_step.host_has_avx512()
             else "optimised CPU step (AVX2)",
-            "sample": "%d steps of the %dx%d FP64 RT lattice after 1 warm-up step (%.2f s)"
-                      % (steps, lx, ly, dt)}
+            "sample": "%d steps of the %dx%d FP64 RT lattice after 2 warm-up steps (%.2f s), %s"
+                      % (steps, lx, ly, dt, cpu_model())}
 
 
 def main(argv=None) -> int:
@@ -636,6 +638,10 @@ def main(argv=None) -> int:
                 "GB/s": round(bytes_per_site("fp32") * sites / (t32 / args.steps) / 1e9, 1),
                 "error_vs_fp64_gpu": {k: float("%.3g" % v) for k, v in errs.items()},
                 "error_after_steps": args.warmup + args.steps}
+            if prec == "fp32s_f32sum":
+                out[key]["note"] = ("ablation: Hermite sums in FP32; its error grows past 1e-5 "
+                                    "within ~500 steps, so the FP32 form that meets 1e-5 keeps "
+                                    "the sums in FP64 (fp32_shifted)")
             fl = counted_fp32_mode_flops(prec)
             if fl is not None:
                 rate = sites / (t32 / args.steps) / 1e12
