@@ -17,7 +17,8 @@ import oracle
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "d2q37_oracle.cpp")
 PINS = ["tests/test_oracle_model.py", "tests/test_oracle_collide.py",
-        "tests/test_oracle_stream.py", "tests/test_oracle_physics.py"]
+        "tests/test_oracle_stream.py", "tests/test_oracle_physics.py",
+        "tests/test_oracle_derived.py"]
 
 MUTANTS = {
     "equilibrium_drops_theta_squared": (
@@ -42,6 +43,10 @@ MUTANTS = {
     "bgk_rate_inverted": (
         "h[l] = (1.0 - 1.0 / tau) * ft[l] + feq[l] / tau;",
         "h[l] = (1.0 - tau) * ft[l] + feq[l] * tau;"),
+    "kinetic_energy_drops_half": (
+        "ke += 0.5 * rho * (ux * ux + uy * uy);", "ke += rho * (ux * ux + uy * uy);"),
+    "step_sites_reversed_gather": (
+        "const int xs_ = wrap(x - M.cx[l], lx);", "const int xs_ = wrap(x + M.cx[l], lx);"),
     "quadrature_redundant_condition": (
         "{4, 2}, {8, 0}, {6, 2}, {4, 4}};", "{4, 2}, {8, 0}, {6, 2}, {2, 6}};"),
 }
