@@ -13,7 +13,7 @@
 //                    towards the local equilibrium with rate 1/tau.
 //   Sec. 2, Eq. (2)  rho = sum f, rho u = sum c f, D rho T = sum |c-u|^2 f,
 //                    perfect-gas equation of state p = rho T, D = 2.
-//   Sec. 2           "populations move up to three lattice sites";
+//   Sec. 2           populations travel at most three sites per step;
 //                    propagate, then bc (top/bottom walls at constant
 //                    temperature and zero velocity), then collide; periodic x
 //                    through three halo columns; a projection onto Hermite
@@ -48,8 +48,8 @@ using quad = __float128;
 // ---------------------------------------------------------------------------
 // Velocity set and quadrature weights.
 //
-// Reading: the paper gives only "up to three lattice sites" and the two
-// offsets of Fig. 4.  The set is every integer vector c with |c|^2 <= 10
+// Reading: the paper states only that populations travel at most three sites,
+// and Fig. 4 shows two offsets.  The set is every integer vector c with |c|^2 <= 10
 // (37 vectors: families (0,0) (1,0) (1,1) (2,0) (2,1) (2,2) (3,0) (3,1) with
 // their images).  Labels follow cx descending, then cy ascending, which puts
 // (3,-1) at l=0 and (3,0) at l=1 as in Fig. 4 and makes l and 36-l opposite.
@@ -408,8 +408,8 @@ void boundary(int lx, int ly, double t_bottom, double t_top, S* ft) {
 // which adds exactly rho g to the momentum and rho (2 u.g + |g|^2) to
 // sum |c|^2 f per step.  Then the BGK value
 //   h_l = (1 - 1/tau) f_l + f^eq_l(rho, u*, T*) / tau
-// and, with regularize = 1 (reading of the "projection onto a basis of
-// Hermite polynomials"), its projection onto the Hermite polynomials of
+// and, with regularize = 1 (our reading of the Hermite-basis projection that
+// Sec. 2 adds for stability), its projection onto the Hermite polynomials of
 // total order <= 4:
 //   A_pq = sum_m h_m He_p(xi_mx) He_q(xi_my),
 //   f'_l = w_l sum_{p+q<=4} A_pq He_p(xi_lx) He_q(xi_ly) / (p! q!).

@@ -30,7 +30,7 @@ def test_velocity_set_structure(model):
     cx, cy, w, r = model
     vecs = list(zip(cx.tolist(), cy.tolist()))
     assert len(vecs) == 37 and len(set(vecs)) == 37
-    # "up to three lattice sites" (Sec. 2): all hops within 3 in x and y
+    # populations travel at most three sites (Sec. 2): all hops within 3 in x and y
     assert max(abs(np.concatenate([cx, cy]))) == 3
     # opposite pairs and the rest population
     for l in range(37):
