@@ -40,8 +40,6 @@ struct Geom {
   int walls;       // 1: thermal walls in y, 0: periodic y
   long long ps;    // element stride between populations
   long long cs;    // element stride between padded columns
-  long long lps;   // compact adjoint arrays (no halos): stride between populations
-  long long lcs;   // compact adjoint arrays: stride between columns
 };
 
 struct Phys {

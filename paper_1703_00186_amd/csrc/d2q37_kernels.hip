@@ -85,6 +85,18 @@ __device__ __forceinline__ void store_site(S* __restrict__ dst, const Geom& g, l
   for (int l = 0; l < Q; ++l) __builtin_nontemporal_store(S(f[l]), &dst[l * g.ps + site]);
 }
 
+// Adjoint arrays are compact (no halos) in the lattice's layout: [lx][37][ly]
+// for the column layout (population stride below column stride), [37][lx][ly]
+// for SoA.
+struct LamStrides {
+  long long ps, cs;
+};
+
+__device__ __forceinline__ LamStrides lam_strides(const Geom& g) {
+  const long long s2 = (long long)g.lx * g.ly;
+  return g.ps < g.cs ? LamStrides{g.ly, (long long)Q * g.ly} : LamStrides{s2, g.ly};
+}
+
 __device__ __forceinline__ bool on_wall_rows(const Geom& g, int y) {
   return g.walls && (y < 3 || y >= g.ly - 3);
 }
@@ -344,10 +356,11 @@ __global__ __launch_bounds__(kThreads) void k_loss_ke(const double* __restrict__
     const double u2 = m.ux * m.ux + m.uy * m.uy;
     ke = 0.5 * m.rho * u2;
     if (lambda) {
-      const long long s = (long long)x * g.lcs + y;
+      const LamStrides ls = lam_strides(g);
+      const long long s = (long long)x * ls.cs + y;
 #pragma unroll
       for (int l = 0; l < Q; ++l)
-        lambda[l * g.lps + s] = R * (EX[l] * m.ux + EY[l] * m.uy) - 0.5 * u2;
+        lambda[l * ls.ps + s] = R * (EX[l] * m.ux + EY[l] * m.uy) - 0.5 * u2;
     }
   }
   const double tot = block_sum(ke);
@@ -414,10 +427,11 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const double* __restrict__
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
   // tape: [4][lx][ly]; lambda: compact, in the lattice's layout
   const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
-  const long long sl = (long long)x * g.lcs + y;
+  const LamStrides ls = lam_strides(g);
+  const long long sl = (long long)x * ls.cs + y;
   double lam[Q];
 #pragma unroll
-  for (int l = 0; l < Q; ++l) lam[l] = lam_in[l * g.lps + sl];
+  for (int l = 0; l < Q; ++l) lam[l] = lam_in[l * ls.ps + sl];
   const double rho = tape[s], jx = tape[S2 + s], jy = tape[2 * S2 + s], e = tape[3 * S2 + s];
   const double inv = 1.0 / rho;
   const double ux = jx * inv, uy = jy * inv;
@@ -486,14 +500,14 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const double* __restrict__
     xs += xs < 0 ? g.lx : (xs >= g.lx ? -g.lx : 0);
     int yd = ys;
     if (!g.walls) yd += yd < 0 ? g.ly : (yd >= g.ly ? -g.ly : 0);
-    lam_out[l * g.lps + (long long)xs * g.lcs + yd] = mu[l];
+    lam_out[l * ls.ps + (long long)xs * ls.cs + yd] = mu[l];
   }
   // Populations leaving through a wall from this site reach no site: zero.
   if (on_wall_rows(g, y)) {
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
       const int yd = y + EY[l];
-      if (yd < 0 || yd >= g.ly) lam_out[l * g.lps + sl] = 0.0;
+      if (yd < 0 || yd >= g.ly) lam_out[l * ls.ps + sl] = 0.0;
     }
   }
 }
@@ -505,10 +519,11 @@ __global__ __launch_bounds__(kThreads) void k_init_adjoint(
     double* __restrict__ dT, Geom g, int by, int bx, int nty, unsigned nb) {
   int x, y;
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
-  const long long s = (long long)x * g.ly + y, sl = (long long)x * g.lcs + y;
+  const LamStrides ls = lam_strides(g);
+  const long long s = (long long)x * g.ly + y, sl = (long long)x * ls.cs + y;
   double lam[Q];
 #pragma unroll
-  for (int l = 0; l < Q; ++l) lam[l] = lam0[l * g.lps + sl];
+  for (int l = 0; l < Q; ++l) lam[l] = lam0[l * ls.ps + sl];
   double L[5][5];
   adjoint_project(lam, L);
   const EqGrad G = equilibrium_grad(L, rho[s], ux[s], uy[s], T[s] - 1.0);

@@ -107,13 +107,9 @@ Geom make_geom(const lb_lattice& lat) {
   if (lat.layout == LB_LAYOUT_SOA) {
     g.ps = (long long)g.nx * g.ny;
     g.cs = g.ny;
-    g.lps = (long long)g.lx * g.ly;
-    g.lcs = g.ly;
   } else {
     g.ps = g.ny;
     g.cs = (long long)d2q37::Q * g.ny;
-    g.lps = g.ly;
-    g.lcs = (long long)d2q37::Q * g.ly;
   }
   return g;
 }
