@@ -231,9 +231,13 @@ def _parity_workload(P, torch) -> dict:
     lb = LB(lx, ly, *f)
     lb.step(n)
     m = host_moments(lb, torch)
+    t0 = time.perf_counter()
     ref = oracle.moments(oracle.run(oracle.init_feq(*f), P, n))
+    t_or = time.perf_counter() - t0
     rec = {"workload": "parity 256x128", "lattice": [lx, ly], "steps": n, "precision": "fp64",
-           "error_vs_oracle": field_errors(m, ref)}
+           "error_vs_oracle": field_errors(m, ref),
+           "oracle": {"MLUPS": round(mlups(lx * ly * n, t_or), 2), "seconds": round(t_or, 3),
+                      "threads": oracle.get_threads()}}
     log("workloads: %s" % rec)
     return rec
 
@@ -263,8 +267,12 @@ def _fp32_workload(args, P, torch) -> dict:
     fs = workload.rt_fields(lxs, lxs, seed=workload.config_seed(3))[:4]
     lb = LB(lxs, lxs, *fs, precision="fp32s")
     lb.step(n)
-    rec["fp32s"]["error_vs_oracle_256x256"] = field_errors(
-        host_moments(lb, torch), oracle.moments(oracle.run(oracle.init_feq(*fs), P, n)))
+    t0 = time.perf_counter()
+    ref = oracle.moments(oracle.run(oracle.init_feq(*fs), P, n))
+    t_or = time.perf_counter() - t0
+    rec["fp32s"]["error_vs_oracle_256x256"] = field_errors(host_moments(lb, torch), ref)
+    rec["oracle_256x256"] = {"MLUPS": round(mlups(lxs * lxs * n, t_or), 2),
+                             "seconds": round(t_or, 2), "threads": oracle.get_threads()}
     del lb
     torch.cuda.empty_cache()
     log("workloads: %s" % rec)
