@@ -68,7 +68,8 @@ hipError_t launch_observables(const void* src, double* partial, double* profiles
 // Adjoint (FP64 buffers).
 // KE of the padded state: per-block partial sums into `partials` (size
 // returned by loss_ke_blocks), then reduced into *ke; lambda (optional)
-// compact [37][lx][ly].
+// compact, in the lattice's layout ([lx][37][ly] column, [37][lx][ly] SoA),
+// as are the adjoint arrays below.
 int loss_ke_blocks(const Geom& g);
 hipError_t launch_loss_ke(const void* src, double* ke, double* lambda, double* partials,
                           const Geom& g, hipStream_t s);
