@@ -9,8 +9,10 @@ CPU fallback: if the library is missing, loading fails with an error.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
+import numpy as np
 import torch
 
 from . import build as _build
@@ -207,9 +209,7 @@ class LB:
         return (t.permute(1, 0, 2) if self.layout == "column" else t).contiguous()
 
     def _check_lambda(self, lam: torch.Tensor):
-        if (tuple(lam.shape) != self.lambda_shape or lam.dtype != torch.float64
-                or not lam.is_contiguous()):
-            raise ValueError("adjoint array must be contiguous float64 %s" % (self.lambda_shape,))
+        self._expect(lam, self.lambda_shape, torch.float64, "adjoint array")
 
     # -- the step ------------------------------------------------------------
     def set_params(self, **params):
@@ -261,15 +261,34 @@ class LB:
         _check(self.lib.lb_moments(self.ctx, *[_ptr(t) for t in out]))
         return tuple(out)
 
+    # -- argument checks: the library trusts the sizes of the buffers it gets --
+    def _expect(self, t, shape, dtype, what: str):
+        if (not isinstance(t, torch.Tensor) or tuple(t.shape) != tuple(shape)
+                or t.dtype != dtype or t.device != self.device or not t.is_contiguous()):
+            raise ValueError("%s must be a contiguous %s tensor of shape %s on %s"
+                             % (what, dtype, tuple(shape), self.device))
+
+    def _state_arg(self, f, what: str) -> torch.Tensor:
+        """A [37, lx, ly] array in the state's dtype (FP64, or the shifted FP32
+        values), moved to the device; no dtype conversion."""
+        t = torch.as_tensor(f)
+        if tuple(t.shape) != (Q, self.lx, self.ly) or t.dtype != self.state_dtype:
+            raise ValueError("%s must be %s of shape %s" % (what, self.state_dtype,
+                                                            (Q, self.lx, self.ly)))
+        return t.to(self.device).contiguous()
+
     def get_state(self, out=None) -> torch.Tensor:
         self._sync_stream()
-        out = self.new_populations() if out is None else out
+        if out is None:
+            out = self.new_populations()
+        else:
+            self._expect(out, (Q, self.lx, self.ly), self.state_dtype, "out")
         _check(self.lib.lb_get_state(self.ctx, _ptr(out)))
         return out
 
     def set_state(self, f: torch.Tensor):
         self._sync_stream()
-        f = f.to(self.device, self.state_dtype).contiguous()
+        f = self._state_arg(f, "state")
         _check(self.lib.lb_set_state(self.ctx, _ptr(f)))
 
     def populations(self) -> torch.Tensor:
@@ -303,7 +322,7 @@ class LB:
 
     def set_scratch(self, f: torch.Tensor):
         self._sync_stream()
-        f = f.to(self.device, self.state_dtype).contiguous()
+        f = self._state_arg(f, "scratch")
         _check(self.lib.lb_set_scratch(self.ctx, _ptr(f)))
 
     # -- in-situ observables ------------------------------------------------
@@ -317,6 +336,8 @@ class LB:
 
     def run_observed(self, n: int, every: int) -> torch.Tensor:
         """n steps; the 4 scalars after every `every` steps, [n // every, 4]."""
+        if int(every) <= 0 or int(n) < 0:
+            raise ValueError("need n >= 0 and every > 0")
         self._sync_stream()
         series = torch.empty((max(n // every, 1), N_SCALARS), dtype=torch.float64,
                              device=self.device)
@@ -329,8 +350,10 @@ class LB:
 
     def step_record(self, n: int, tape: torch.Tensor):
         self._sync_stream()
-        if tape.shape[0] < n or tuple(tape.shape[1:]) != (4, self.lx, self.ly):
+        if (not isinstance(tape, torch.Tensor) or tape.dim() != 4 or tape.shape[0] < n
+                or tuple(tape.shape[1:]) != (4, self.lx, self.ly)):
             raise ValueError("tape must be [>=n, 4, lx, ly]")
+        self._expect(tape, tape.shape, torch.float64, "tape")
         _check(self.lib.lb_step_record(self.ctx, int(n), _ptr(tape)))
 
     def loss_ke(self, with_lambda: bool = True):
@@ -341,6 +364,7 @@ class LB:
         return ke, lam
 
     def adjoint_step(self, tape_j: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor):
+        self._expect(tape_j, (4, self.lx, self.ly), torch.float64, "tape_j")
         self._check_lambda(lam_in)
         self._check_lambda(lam_out)
         self._sync_stream()
@@ -355,6 +379,30 @@ class LB:
         _check(self.lib.lb_init_adjoint(self.ctx, *[_ptr(f) for f in fields], _ptr(lam0),
                                         *[_ptr(t) for t in out]))
         return tuple(out)
+
+    # -- checkpoints on disk --------------------------------------------------
+    def save_checkpoint(self, path: str) -> None:
+        """Writes the state (compact [37, lx, ly] in the context's precision)
+        and the lattice and parameters to an .npz file of plain arrays."""
+        meta = {"lx": self.lx, "ly": self.ly, "precision": self.precision,
+                "layout": self.layout, "ybc": int(self.lat.ybc), "params": self.params}
+        state = self.get_state()
+        torch.cuda.synchronize(self.device)
+        np.savez(path, state=state.cpu().numpy(), meta=np.array(json.dumps(meta)))
+
+    def load_checkpoint(self, path: str) -> dict:
+        """Restores a state written by save_checkpoint into this context (same
+        lattice size, precision and y boundary); returns the saved metadata.
+        The parameters of this context are left as they are."""
+        with np.load(path, allow_pickle=False) as z:
+            meta = json.loads(str(z["meta"]))
+            state = z["state"]
+        if (meta["lx"], meta["ly"], meta["precision"], meta["ybc"]) != (
+                self.lx, self.ly, self.precision, int(self.lat.ybc)):
+            raise ValueError("checkpoint is for %dx%d %s ybc=%d" % (
+                meta["lx"], meta["ly"], meta["precision"], meta["ybc"]))
+        self.set_state(torch.from_numpy(state))
+        return meta
 
     def close(self):
         if getattr(self, "ctx", None) and self.ctx.value:

@@ -206,3 +206,37 @@ def test_rest_state_at_the_wall_temperature_is_a_fixed_point(kernel, T_wall):
     lb.step(25)
     f = host(lb.populations())
     assert np.abs(f - f0).max() <= 1e-13 * np.abs(f0).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+def test_checkpoint_file_round_trip(tmp_path, precision):
+    """save_checkpoint / load_checkpoint: the resumed run is bit-identical."""
+    lb, fields = make(48, 40, precision=precision)
+    lb.step(7)
+    path = str(tmp_path / "ck.npz")
+    lb.save_checkpoint(path)
+    lb.step(9)
+    after = lb.get_state().clone()
+    other, _ = make(48, 40, precision=precision, seed=99)
+    meta = other.load_checkpoint(path)
+    assert meta["precision"] == precision
+    other.step(9)
+    assert torch.equal(other.get_state(), after)
+    wrong, _ = make(40, 48, precision=precision)
+    with pytest.raises(ValueError):
+        wrong.load_checkpoint(path)
+
+
+def test_state_arguments_are_checked():
+    lb, _ = make(20, 16)
+    with pytest.raises(ValueError):
+        lb.set_state(torch.zeros((37, 20, 15), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        lb.set_state(torch.zeros((37, 20, 16), dtype=torch.float32))
+    with pytest.raises(ValueError):
+        lb.get_state(out=torch.empty((37, 20, 16), dtype=torch.float64))  # host tensor
+    with pytest.raises(ValueError):
+        lb.step_record(2, torch.empty((2, 4, 20, 16), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        lb.adjoint_step(torch.empty((4, 20, 15), dtype=torch.float64, device="cuda"),
+                        lb.new_lambda(), lb.new_lambda())
