@@ -237,6 +237,8 @@ class LB:
         """Records n (even) fused steps into a CUDA/HIP graph on a side
         stream; graph.replay() then advances this lattice by n steps.
 
+        Two ordinary steps run first (the lattice advances by 2), so that the
+        halos are valid and the buffer roles settled when recording starts.
         The buffers swap once per step, so an even n returns the state to the
         buffer it started in, which is what lets the same graph run again.
         Only the fused path without check_finite is capturable.
