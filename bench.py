@@ -150,6 +150,39 @@ def time_steps(lb, steps: int, torch) -> float:
     return e0.elapsed_time(e1) / 1e3
 
 
+def time_adjoint(lb, steps: int, torch) -> dict:
+    """The adjoint on the headline lattice with a full tape: `steps` steps
+    recorded (fused step + 4-moment tape, 624 B/site), then `steps` transposed
+    steps (k_adjoint, 624 B/site); HIP events on the kernels' stream.  The
+    lattice advances by `steps`."""
+    sites = lb.lx * lb.ly
+    tape = lb.new_tape(steps)
+    lam, spare = lb.new_lambda(), lb.new_lambda()
+    lb.step_record(2, tape)  # warm-up of both kernels
+    lb.adjoint_step(tape[0], lam.zero_(), spare)
+    s = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(s)
+    lb.step_record(steps, tape)
+    ev[1].record(s)
+    _, lam = lb.loss_ke(with_lambda=True)
+    ev[2].record(s)
+    for j in range(steps - 1, -1, -1):
+        lb.adjoint_step(tape[j], lam, spare)
+        lam, spare = spare, lam
+    ev[3].record(s)
+    torch.cuda.synchronize()
+    t_rec = ev[0].elapsed_time(ev[1]) / 1e3 / steps
+    t_adj = ev[2].elapsed_time(ev[3]) / 1e3 / steps
+    return {"steps": steps, "record_ms_per_step": round(t_rec * 1e3, 5),
+            "record_GB/s": round(624 * sites / t_rec / 1e9, 1),
+            "adjoint_ms_per_step": round(t_adj * 1e3, 5),
+            "adjoint_GB/s": round(624 * sites / t_adj / 1e9, 1),
+            "adjoint_frac": round(624 * sites / t_adj / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "k_adjoint: lambda in 296 + tape 32 + lambda out 296 B/site"}
+
+
 def time_split_kernels(lb, steps: int, torch) -> dict:
     """Per-kernel seconds of the split path (halo, propagate, bc, collide)."""
     s = torch.cuda.current_stream()
@@ -545,6 +578,8 @@ def main(argv=None) -> int:
     ap.add_argument("--ly", type=int, default=2048)
     ap.add_argument("--layout", default="column", choices=["soa", "column"])
     ap.add_argument("--split-steps", type=int, default=50)
+    ap.add_argument("--adjoint-steps", type=int, default=50,
+                    help="steps of the full-tape adjoint timing on the headline lattice")
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -632,6 +667,8 @@ def main(argv=None) -> int:
         lb.set_params(kernel="fused")
         lb.step(args.warmup + args.steps)
         m64 = host_moments(lb, torch)
+        out["adjoint_fp64"] = time_adjoint(lb, args.adjoint_steps, torch)
+        log("bench: adjoint %s" % json.dumps(out["adjoint_fp64"]))
         del lb
         torch.cuda.empty_cache()
         for key, prec in (("fp32_shifted", "fp32s"), ("fp32_shifted_f32sum", "fp32s_f32sum")):
