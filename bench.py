@@ -153,34 +153,45 @@ def time_steps(lb, steps: int, torch) -> float:
 def time_adjoint(lb, steps: int, torch) -> dict:
     """The adjoint on the headline lattice with a full tape: `steps` steps
     recorded (fused step + 4-moment tape, 624 B/site), then `steps` transposed
-    steps (k_adjoint, 624 B/site); HIP events on the kernels' stream.  The
-    lattice advances by `steps`."""
+    steps in one lb_adjoint_run (gather form, k_adjoint_mu: 624 B/site) and,
+    for comparison, as single lb_adjoint_step calls (scatter form, k_adjoint);
+    HIP events on the kernels' stream.  The lattice advances by `steps`."""
     sites = lb.lx * lb.ly
     tape = lb.new_tape(steps)
     lam, spare = lb.new_lambda(), lb.new_lambda()
-    lb.step_record(2, tape)  # warm-up of both kernels
+    lb.step_record(2, tape)  # warm-up of the kernels
     lb.adjoint_step(tape[0], lam.zero_(), spare)
+    lb.adjoint_run(tape, lam, 2)
     s = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     ev[0].record(s)
     lb.step_record(steps, tape)
     ev[1].record(s)
     _, lam = lb.loss_ke(with_lambda=True)
+    lam1 = lam.clone()
     ev[2].record(s)
-    for j in range(steps - 1, -1, -1):
-        lb.adjoint_step(tape[j], lam, spare)
-        lam, spare = spare, lam
+    lb.adjoint_run(tape, lam, steps)
     ev[3].record(s)
+    ev[4].record(s)
+    for j in range(steps - 1, -1, -1):
+        lb.adjoint_step(tape[j], lam1, spare)
+        lam1, spare = spare, lam1
+    ev[5].record(s)
     torch.cuda.synchronize()
+    same = bool(torch.equal(lam, lam1))
     t_rec = ev[0].elapsed_time(ev[1]) / 1e3 / steps
-    t_adj = ev[2].elapsed_time(ev[3]) / 1e3 / steps
+    t_run = ev[2].elapsed_time(ev[3]) / 1e3 / steps
+    t_one = ev[4].elapsed_time(ev[5]) / 1e3 / steps
+    gbs = lambda t: round(624 * sites / t / 1e9, 1)  # noqa: E731
     return {"steps": steps, "record_ms_per_step": round(t_rec * 1e3, 5),
-            "record_GB/s": round(624 * sites / t_rec / 1e9, 1),
-            "adjoint_ms_per_step": round(t_adj * 1e3, 5),
-            "adjoint_GB/s": round(624 * sites / t_adj / 1e9, 1),
-            "adjoint_frac": round(624 * sites / t_adj / 1e9 / HBM_PEAK_GBS, 4),
-            "note": "k_adjoint: lambda in 296 + tape 32 + lambda out 296 B/site"}
+            "record_GB/s": gbs(t_rec),
+            "adjoint_ms_per_step": round(t_run * 1e3, 5), "adjoint_GB/s": gbs(t_run),
+            "adjoint_frac": round(624 * sites / t_run / 1e9 / HBM_PEAK_GBS, 4),
+            "single_step_ms_per_step": round(t_one * 1e3, 5), "single_step_GB/s": gbs(t_one),
+            "run_equals_single_steps": same,
+            "note": "lambda in 296 + tape 32 + lambda out 296 B/site; adjoint_*: lb_adjoint_run "
+                    "(gather form), single_step_*: lb_adjoint_step (scatter form)"}
 
 
 def time_split_kernels(lb, steps: int, torch) -> dict:
@@ -430,13 +441,10 @@ def _production_workload(args, torch) -> dict:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     tape = lb.new_tape(k)
-    spare = lb.new_lambda()
     for ck in reversed(ckpts):
         lb.set_state(ck)
         lb.step_record(k, tape)
-        for j in range(k - 1, -1, -1):
-            lb.adjoint_step(tape[j], lam, spare)
-            lam, spare = spare, lam
+        lb.adjoint_run(tape, lam, k)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     extra = device_bytes_in_use(torch) - base
@@ -448,7 +456,7 @@ def _production_workload(args, torch) -> dict:
     # the same gradient from a full tape of the n_adj steps (32 B per site and
     # step) instead of checkpoints and recomputation
     ck0, lam_ckpt = ckpts[0], lam
-    del ckpts, tape, spare
+    del ckpts, tape
     torch.cuda.empty_cache()
     base = device_bytes_in_use(torch)
     lb.set_state(ck0)
@@ -459,10 +467,7 @@ def _production_workload(args, torch) -> dict:
     ke, lam = lb.loss_ke(with_lambda=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    spare = lb.new_lambda()
-    for j in range(n_adj - 1, -1, -1):
-        lb.adjoint_step(tape[j], lam, spare)
-        lam, spare = spare, lam
+    lb.adjoint_run(tape, lam, n_adj)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     extra = device_bytes_in_use(torch) - base
@@ -474,7 +479,7 @@ def _production_workload(args, torch) -> dict:
         "tape_lambda_GB": round(extra / 1e9, 3),
         "lambda_vs_checkpointed": float((lam - lam_ckpt).norm().cpu() / lam_ckpt.norm().cpu())}
     rec["peak_device_GB"] = round(torch.cuda.max_memory_allocated() / 1e9, 2)
-    del lb, ck0, tape, spare, lam, lam_ckpt
+    del lb, ck0, tape, lam, lam_ckpt
     torch.cuda.empty_cache()
     log("workloads: %s" % rec)
     return rec

@@ -95,7 +95,7 @@ typedef struct lb_params {
 typedef struct lb_ctx lb_ctx;
 
 const char* lb_last_error(void);
-/* Interface version: 2 (adjoint arrays in the lattice's layout). */
+/* Interface version: 3 (adjoint arrays in the lattice's layout; lb_adjoint_run). */
 int lb_version(void);
 
 /* Bytes of device workspace lb_init needs for this lattice (two padded
@@ -196,6 +196,16 @@ int lb_run_observed(lb_ctx* ctx, int n, int every, double* series);
  * and lambda_out are distinct buffers; every element of lambda_out is
  * written.
  *
+ * lb_adjoint_run: n transposed steps in one call, lambda^n -> lambda^0 in
+ * place in `lambda`, with tape = [n][4][lx][ly] from lb_step_record (tape
+ * step j holds the moments of the step from f^j to f^{j+1}).  The same
+ * arithmetic as n calls of lb_adjoint_step, and the same result bit for bit,
+ * but P^T is applied as a gather by the following step: between steps the
+ * adjoint lives in two padded FP64 buffers laid out like the state, which the
+ * caller provides as `workspace` (256-byte aligned, at least the size from
+ * lb_adjoint_workspace_bytes; its previous contents do not matter).  n = 0
+ * leaves lambda unchanged.
+ *
  * lb_init_adjoint: given lambda0 = dL/df^0 and the initial fields
  * (rho0, ux0, uy0, T0) the state was built from, writes dL/d(rho0, ux0, uy0,
  * T0) of the initial equilibrium f^0 = f^eq(rho0, u0, T0); all [lx][ly],
@@ -204,6 +214,9 @@ int lb_step_record(lb_ctx* ctx, int n, double* tape);
 int lb_loss_ke(lb_ctx* ctx, double* ke_dev, double* lambda);
 int lb_adjoint_step(lb_ctx* ctx, const double* tape_j, const double* lambda_in,
                     double* lambda_out);
+int lb_adjoint_workspace_bytes(lb_ctx* ctx, size_t* bytes);
+int lb_adjoint_run(lb_ctx* ctx, int n, const double* tape, double* lambda, void* workspace,
+                   size_t workspace_bytes);
 int lb_init_adjoint(lb_ctx* ctx, const double* rho0, const double* ux0,
                     const double* uy0, const double* T0, const double* lambda0,
                     double* drho0, double* dux0, double* duy0, double* dT0);

@@ -8,7 +8,9 @@ fields.  Forward runs the fused step and keeps the state every
 restores the segment's checkpoint, recomputes the segment while recording the
 four pre-collision moments of every site and step (lb_step_record), then
 applies the transposed steps (lb_adjoint_step) from the segment's end to its
-start, and finally maps dL/df^0 to dL/d(rho0, u0, T0) (lb_init_adjoint).
+start (lb_adjoint_run: the transposed steps of a segment in one call, in
+gather form), and finally maps dL/df^0 to dL/d(rho0, u0, T0)
+(lb_init_adjoint).
 With ``checkpoint_every=0`` the forward pass records the moments of every
 step instead (memory: 32 bytes per site and step, e.g. 1.7 GB for 200 steps of
 512 x 512, 107 GB for 100 steps of 8192 x 4096) and the backward pass only
@@ -55,12 +57,9 @@ class _KineticEnergy(torch.autograd.Function):
     def backward(ctx, grad):
         lb: LB = ctx.lb
         rho0, ux0, uy0, T0 = ctx.saved_tensors
-        spare = lb.new_lambda()
         if ctx.tape is not None:
             lam = ctx.lam.mul_(grad)
-            for j in range(ctx.nsteps - 1, -1, -1):
-                lb.adjoint_step(ctx.tape[j], lam, spare)
-                lam, spare = spare, lam
+            lb.adjoint_run(ctx.tape, lam, ctx.nsteps)
             d = lb.init_adjoint(rho0, ux0, uy0, T0, lam)
             ctx.lb = ctx.tape = ctx.lam = None
             return d[0], d[1], d[2], d[3], None, None, None
@@ -78,9 +77,7 @@ class _KineticEnergy(torch.autograd.Function):
             if lam is None:  # last segment: its end is the final state
                 _, lam = lb.loss_ke(with_lambda=True)
                 lam.mul_(grad)
-            for j in range(n - 1, -1, -1):
-                lb.adjoint_step(tape[j], lam, spare)
-                lam, spare = spare, lam
+            lb.adjoint_run(tape, lam, n)
         d = lb.init_adjoint(rho0, ux0, uy0, T0, lam)
         ctx.lb = None
         ctx.ckpts = None

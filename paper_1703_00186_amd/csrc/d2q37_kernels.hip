@@ -417,22 +417,14 @@ __device__ __forceinline__ void adjoint_project(const double (&lam)[Q], double (
 }
 
 // lambda_out = P^T B^T C^T lambda_in for one step (scatter form).
+// B^T C(m)^T of one site: lam holds lambda^{j+1} at the site's arriving
+// populations, m = (rho, j_x, j_y, sum |c|^2 f) the pre-collision moments of
+// step j; on return mu holds the adjoint of the propagated populations
+// (zero for those a wall supplied).
 template <bool kReg>
-__global__ __launch_bounds__(kThreads) void k_adjoint(const double* __restrict__ tape,
-                                                      const double* __restrict__ lam_in,
-                                                      double* __restrict__ lam_out, Geom g,
-                                                      Phys P, int by, int bx, int nty,
-                                                      unsigned nb) {
-  int x, y;
-  if (!site_of(g, by, bx, nty, nb, x, y)) return;
-  // tape: [4][lx][ly]; lambda: compact, in the lattice's layout
-  const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
-  const LamStrides ls = lam_strides(g);
-  const long long sl = (long long)x * ls.cs + y;
-  double lam[Q];
-#pragma unroll
-  for (int l = 0; l < Q; ++l) lam[l] = lam_in[l * ls.ps + sl];
-  const double rho = tape[s], jx = tape[S2 + s], jy = tape[2 * S2 + s], e = tape[3 * S2 + s];
+__device__ __forceinline__ void adjoint_site(const double (&lam)[Q], double rho, double jx,
+                                             double jy, double e, const Geom& g, const Phys& P,
+                                             int y, double (&mu)[Q]) {
   const double inv = 1.0 / rho;
   const double ux = jx * inv, uy = jy * inv;
   const double u2 = ux * ux + uy * uy;
@@ -462,7 +454,6 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const double* __restrict__
   B[0][1] += g01;
   B[2][0] += ge2;
   B[0][2] += ge2;
-  double mu[Q];
   expand<double>(B, mu);
   if (!kReg) {
 #pragma unroll
@@ -491,6 +482,26 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const double* __restrict__
       mu[l] = unknown ? 0.0 : mu[l] + add;
     }
   }
+}
+
+template <bool kReg>
+__global__ __launch_bounds__(kThreads) void k_adjoint(const double* __restrict__ tape,
+                                                      const double* __restrict__ lam_in,
+                                                      double* __restrict__ lam_out, Geom g,
+                                                      Phys P, int by, int bx, int nty,
+                                                      unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  // tape: [4][lx][ly]; lambda: compact, in the lattice's layout
+  const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
+  const LamStrides ls = lam_strides(g);
+  const long long sl = (long long)x * ls.cs + y;
+  double lam[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) lam[l] = lam_in[l * ls.ps + sl];
+  double mu[Q];
+  adjoint_site<kReg>(lam, tape[s], tape[S2 + s], tape[2 * S2 + s], tape[3 * S2 + s], g, P, y,
+                     mu);
   // P^T: the population that arrived here came from (x - e_lx, y - e_ly).
 #pragma unroll
   for (int l = 0; l < Q; ++l) {
@@ -510,6 +521,71 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(const double* __restrict__
       if (yd < 0 || yd >= g.ly) lam_out[l * ls.ps + sl] = 0.0;
     }
   }
+}
+
+// Gather form of a run of adjoint steps.  mu^j = B^T C(m_j)^T lambda^{j+1}
+// is kept where the populations arrived, in a padded buffer laid out like the
+// state (x halos written by the edge columns, rows beyond the walls zero), and
+// P^T is applied when the next kernel reads it:
+// lambda^j_l(z) = mu^j_l(z + e_l).  So every load is a shifted coalesced read
+// and every store is aligned, as in the forward step.  kFromCompact: the
+// first kernel of a run reads lambda^{j+1} itself from a compact array.
+template <bool kReg, bool kFromCompact>
+__global__ __launch_bounds__(kThreads) void k_adjoint_mu(const double* __restrict__ tape,
+                                                         const double* __restrict__ in,
+                                                         double* __restrict__ mu_out, Geom g,
+                                                         Phys P, int by, int bx, int nty,
+                                                         unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
+  const long long site = padded<double>(g, x + HX, y + g.hy);
+  double lam[Q];
+  if (kFromCompact) {
+    const LamStrides ls = lam_strides(g);
+    const long long sl = (long long)x * ls.cs + y;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) lam[l] = in[l * ls.ps + sl];
+  } else {
+#pragma unroll
+    for (int l = 0; l < Q; ++l) lam[l] = in[l * g.ps + site + EX[l] * g.cs + EY[l]];
+  }
+  double mu[Q];
+  adjoint_site<kReg>(lam, tape[s], tape[S2 + s], tape[2 * S2 + s], tape[3 * S2 + s], g, P, y,
+                     mu);
+  store_site<double, double>(mu_out, g, site, mu);
+  if (x < HX) store_site<double, double>(mu_out, g, site + (long long)g.lx * g.cs, mu);
+  if (x >= g.lx - HX) store_site<double, double>(mu_out, g, site - (long long)g.lx * g.cs, mu);
+}
+
+// Last kernel of a run: lambda^j_l(z) = mu^j_l(z + e_l) into a compact array.
+__global__ __launch_bounds__(kThreads) void k_adjoint_gather(const double* __restrict__ mu,
+                                                             double* __restrict__ lam, Geom g,
+                                                             int by, int bx, int nty,
+                                                             unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const long long site = padded<double>(g, x + HX, y + g.hy);
+  const LamStrides ls = lam_strides(g);
+  const long long sl = (long long)x * ls.cs + y;
+#pragma unroll
+  for (int l = 0; l < Q; ++l)
+    __builtin_nontemporal_store(mu[l * g.ps + site + EX[l] * g.cs + EY[l]], &lam[l * ls.ps + sl]);
+}
+
+// Zero the rows beyond the walls (padded rows outside [0, ly)) of every
+// padded column: there the gather of the adjoint reads the zero that a
+// population leaving the lattice contributes.
+__global__ __launch_bounds__(kThreads) void k_zero_pad_rows(double* __restrict__ buf, Geom g) {
+  const int pad = g.ny - g.ly;  // hy rows below, ny - ly - hy above
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long n = (long long)Q * g.nx * pad;
+  if (i >= n) return;
+  const int r = int(i % pad);
+  const long long lx_ = i / pad;
+  const int l = int(lx_ / g.nx), X = int(lx_ % g.nx);
+  const int Y = r < g.hy ? r : g.ly + r;
+  buf[l * g.ps + (long long)X * g.cs + Y] = 0.0;
 }
 
 __global__ __launch_bounds__(kThreads) void k_init_adjoint(
@@ -834,6 +910,38 @@ hipError_t launch_adjoint_step(const double* tape, const double* lam_in, double*
   else
     hipLaunchKernelGGL(k_adjoint<false>, dim3(t.nb), dim3(kThreads), 0, s, tape, lam_in,
                        lam_out, g, p, t.by, t.bx, t.nty, t.nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_mu(const double* tape, const double* in, bool from_compact, double* mu_out,
+                             const Geom& g, const Phys& p, int regularize, hipStream_t s) {
+  const Tiling t = make_tiling(g.lx, g.ly);
+  const dim3 grid(t.nb), block(kThreads);
+  if (regularize && from_compact)
+    hipLaunchKernelGGL((k_adjoint_mu<true, true>), grid, block, 0, s, tape, in, mu_out, g, p, t.by,
+                       t.bx, t.nty, t.nb);
+  else if (regularize)
+    hipLaunchKernelGGL((k_adjoint_mu<true, false>), grid, block, 0, s, tape, in, mu_out, g, p,
+                       t.by, t.bx, t.nty, t.nb);
+  else if (from_compact)
+    hipLaunchKernelGGL((k_adjoint_mu<false, true>), grid, block, 0, s, tape, in, mu_out, g, p,
+                       t.by, t.bx, t.nty, t.nb);
+  else
+    hipLaunchKernelGGL((k_adjoint_mu<false, false>), grid, block, 0, s, tape, in, mu_out, g, p,
+                       t.by, t.bx, t.nty, t.nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_gather(const double* mu, double* lam, const Geom& g, hipStream_t s) {
+  const Tiling t = make_tiling(g.lx, g.ly);
+  hipLaunchKernelGGL(k_adjoint_gather, dim3(t.nb), dim3(kThreads), 0, s, mu, lam, g, t.by, t.bx,
+                     t.nty, t.nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_pad_rows(double* buf, const Geom& g, hipStream_t s) {
+  const long long n = (long long)Q * g.nx * (g.ny - g.ly);
+  hipLaunchKernelGGL(k_zero_pad_rows, dim3(grid_1d(n)), dim3(kThreads), 0, s, buf, g);
   return hipGetLastError();
 }
 

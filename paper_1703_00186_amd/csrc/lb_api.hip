@@ -208,7 +208,7 @@ extern "C" {
 
 const char* lb_last_error(void) { return g_error.c_str(); }
 
-int lb_version(void) { return 2; }
+int lb_version(void) { return 3; }
 
 int lb_workspace_bytes(const lb_lattice* lat, const lb_params* par, size_t* bytes) {
   int rc = check_lattice(lat);
@@ -453,6 +453,53 @@ int lb_adjoint_step(lb_ctx* ctx, const double* tape_j, const double* lambda_in,
   LB_HIP(d2q37::launch_adjoint_step(tape_j, lambda_in, lambda_out, ctx->g, ctx->p,
                                     ctx->par.regularize, ctx->stream),
          "adjoint_step");
+  return LB_OK;
+}
+
+int lb_adjoint_workspace_bytes(lb_ctx* ctx, size_t* bytes) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  rc = need_fp64(ctx, "lb_adjoint_workspace_bytes");
+  if (rc) return rc;
+  if (!bytes) return fail(LB_E_ARG, "bytes is NULL%s");
+  *bytes = 2 * buffer_bytes(ctx->g, LB_FP64);
+  return LB_OK;
+}
+
+int lb_adjoint_run(lb_ctx* ctx, int n, const double* tape, double* lambda, void* workspace,
+                   size_t workspace_bytes) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  rc = need_fp64(ctx, "lb_adjoint_run");
+  if (rc) return rc;
+  if (n < 0) return fail(LB_E_ARG, "n must be >= 0%s");
+  if (n == 0) return LB_OK;
+  if (!tape || !lambda || !workspace) return fail(LB_E_ARG, "NULL argument%s");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(LB_E_WORKSPACE, "adjoint workspace must be 256-byte aligned%s");
+  const size_t nb = buffer_bytes(ctx->g, LB_FP64);
+  if (workspace_bytes < 2 * nb) return fail(LB_E_WORKSPACE, "adjoint workspace too small%s");
+  double* m0 = static_cast<double*>(workspace);
+  double* m1 = reinterpret_cast<double*>(static_cast<char*>(workspace) + nb);
+  const Geom& g = ctx->g;
+  const bool walls = g.walls != 0;
+  const long long per = 4LL * g.lx * g.ly;
+  const int reg = ctx->par.regularize;
+  if (walls) {  // the gather reads zero beyond the walls
+    LB_HIP(d2q37::launch_zero_pad_rows(m0, g, ctx->stream), "adjoint_run pad rows");
+    LB_HIP(d2q37::launch_zero_pad_rows(m1, g, ctx->stream), "adjoint_run pad rows");
+  }
+  LB_HIP(d2q37::launch_adjoint_mu(tape + per * (n - 1), lambda, true, m0, g, ctx->p, reg,
+                                  ctx->stream),
+         "adjoint_run first step");
+  for (int j = n - 2; j >= 0; --j) {
+    if (!walls) LB_HIP(d2q37::launch_halo(m0, g, LB_FP64, ctx->stream), "adjoint_run halo");
+    LB_HIP(d2q37::launch_adjoint_mu(tape + per * j, m0, false, m1, g, ctx->p, reg, ctx->stream),
+           "adjoint_run step");
+    std::swap(m0, m1);
+  }
+  if (!walls) LB_HIP(d2q37::launch_halo(m0, g, LB_FP64, ctx->stream), "adjoint_run halo");
+  LB_HIP(d2q37::launch_adjoint_gather(m0, lambda, g, ctx->stream), "adjoint_run gather");
   return LB_OK;
 }
 

@@ -103,6 +103,17 @@ void check_context(int precision, int layout, int kernel, int ybc) {
     EXPECT(lb_adjoint_step(ctx, t, la, lbuf) == LB_OK);
     EXPECT(lb_adjoint_step(ctx, t, la, la) == LB_E_ARG);
     EXPECT(lb_adjoint_step(ctx, nullptr, la, lbuf) == LB_E_ARG);
+    size_t adj = 0;
+    EXPECT(lb_adjoint_workspace_bytes(ctx, &adj) == LB_OK && adj >= 2 * 37 * S * 8);
+    EXPECT(lb_adjoint_workspace_bytes(ctx, nullptr) == LB_E_ARG);
+    void* aws = std::aligned_alloc(256, round256(adj));
+    EXPECT(lb_adjoint_run(ctx, 3, t, la, aws, adj) == LB_OK);
+    EXPECT(lb_adjoint_run(ctx, 0, nullptr, nullptr, nullptr, 0) == LB_OK);
+    EXPECT(lb_adjoint_run(ctx, -1, t, la, aws, adj) == LB_E_ARG);
+    EXPECT(lb_adjoint_run(ctx, 3, t, la, aws, adj - 1) == LB_E_WORKSPACE);
+    EXPECT(lb_adjoint_run(ctx, 3, t, la, static_cast<char*>(aws) + 8, adj) == LB_E_WORKSPACE);
+    EXPECT(lb_adjoint_run(ctx, 3, nullptr, la, aws, adj) == LB_E_ARG);
+    std::free(aws);
     EXPECT(lb_init_adjoint(ctx, f, f + S, f + 2 * S, f + 3 * S, lbuf, out.data(), nullptr,
                            nullptr, out.data() + 3 * S) == LB_OK);
     EXPECT(lb_init_adjoint(ctx, f, f + S, f + 2 * S, f + 3 * S, nullptr, out.data(), nullptr,
@@ -111,6 +122,9 @@ void check_context(int precision, int layout, int kernel, int ybc) {
     EXPECT(lb_step_record(ctx, 3, t) == LB_E_STATE);
     EXPECT(lb_loss_ke(ctx, &ke, la) == LB_E_STATE);
     EXPECT(lb_adjoint_step(ctx, t, la, lbuf) == LB_E_STATE);
+    size_t adj = 0;
+    EXPECT(lb_adjoint_workspace_bytes(ctx, &adj) == LB_E_STATE);
+    EXPECT(lb_adjoint_run(ctx, 2, t, la, nullptr, 0) == LB_E_STATE);
     EXPECT(lb_init_adjoint(ctx, f, f + S, f + 2 * S, f + 3 * S, la, nullptr, nullptr, nullptr,
                            nullptr) == LB_E_STATE);
   }
@@ -122,7 +136,7 @@ void check_context(int precision, int layout, int kernel, int ybc) {
 }  // namespace
 
 int main() {
-  EXPECT(lb_version() == 2);
+  EXPECT(lb_version() == 3);
   lb_lattice lat = {64, 48, LB_FP64, LB_Y_WALLS, LB_LAYOUT_COLUMN, 0};
   lb_params par = {0.7, 0.0, -1e-4, 1.5, 0.5, 1.0, 1, LB_KERNEL_FUSED, 0, 0};
   size_t need = 0;
