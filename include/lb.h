@@ -199,12 +199,14 @@ int lb_run_observed(lb_ctx* ctx, int n, int every, double* series);
  * lb_adjoint_run: n transposed steps in one call, lambda^n -> lambda^0 in
  * place in `lambda`, with tape = [n][4][lx][ly] from lb_step_record (tape
  * step j holds the moments of the step from f^j to f^{j+1}).  The same
- * arithmetic as n calls of lb_adjoint_step, and the same result bit for bit,
- * but P^T is applied as a gather by the following step: between steps the
- * adjoint lives in two padded FP64 buffers laid out like the state, which the
- * caller provides as `workspace` (256-byte aligned, at least the size from
- * lb_adjoint_workspace_bytes; its previous contents do not matter).  n = 0
- * leaves lambda unchanged.
+ * arithmetic as n calls of lb_adjoint_step, and the same result bit for bit.
+ * On lattices beyond the Infinity Cache P^T is applied as a gather by the
+ * following step: between steps the adjoint lives in two padded FP64 buffers
+ * laid out like the state (aligned stores instead of the scatter's partial
+ * ones); on lattices of 2^17 sites up to the cache size the steps are the
+ * scatter kernel of lb_adjoint_step.  `workspace`: 256-byte aligned, at least
+ * the size from lb_adjoint_workspace_bytes, previous contents irrelevant.
+ * n = 0 leaves lambda unchanged.
  *
  * lb_init_adjoint: given lambda0 = dL/df^0 and the initial fields
  * (rho0, ux0, uy0, T0) the state was built from, writes dL/d(rho0, ux0, uy0,

@@ -71,10 +71,12 @@ def test_step_transpose(ybc, regularize, layout):
 @pytest.mark.parametrize("ybc,regularize,layout", [
     ("walls", 1, "column"), ("walls", 0, "soa"), ("periodic", 1, "column"),
     ("periodic", 0, "soa")])
-@pytest.mark.parametrize("shape,n", [((37, 70), 1), ((37, 70), 7), ((130, 300), 3)])
+@pytest.mark.parametrize("shape,n", [((37, 70), 1), ((37, 70), 7), ((130, 300), 3),
+                                     ((400, 400), 2), ((400, 400), 3)])
 def test_adjoint_run_equals_single_steps(ybc, regularize, layout, shape, n):
-    """lb_adjoint_run (gather form, padded buffers) gives lb_adjoint_step's
-    result bit for bit; ragged tiles of both tile shapes."""
+    """lb_adjoint_run gives lb_adjoint_step's result bit for bit: the gather
+    form over padded buffers (ragged tiles of both tile shapes) and, at
+    400 x 400, the in-cache scatter form with an even and an odd step count."""
     lx, ly = shape
     lb, P, f, _ = setup(lx, ly, ybc, regularize, layout=layout)
     lb.set_state(torch.from_numpy(f))
