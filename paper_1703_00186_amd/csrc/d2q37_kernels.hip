@@ -575,8 +575,10 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_gather(const double* __res
 
 // Zero the rows beyond the walls (padded rows outside [0, ly)) of every
 // padded column: there the gather of the adjoint reads the zero that a
-// population leaving the lattice contributes.
-__global__ __launch_bounds__(kThreads) void k_zero_pad_rows(double* __restrict__ buf, Geom g) {
+// population leaving the lattice contributes, and the state buffers get
+// finite values in the rows that no step writes.
+template <class S>
+__global__ __launch_bounds__(kThreads) void k_zero_pad_rows(S* __restrict__ buf, Geom g) {
   const int pad = g.ny - g.ly;  // hy rows below, ny - ly - hy above
   const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
   const long long n = (long long)Q * g.nx * pad;
@@ -585,7 +587,7 @@ __global__ __launch_bounds__(kThreads) void k_zero_pad_rows(double* __restrict__
   const long long lx_ = i / pad;
   const int l = int(lx_ / g.nx), X = int(lx_ % g.nx);
   const int Y = r < g.hy ? r : g.ly + r;
-  buf[l * g.ps + (long long)X * g.cs + Y] = 0.0;
+  buf[l * g.ps + (long long)X * g.cs + Y] = S(0);
 }
 
 __global__ __launch_bounds__(kThreads) void k_init_adjoint(
@@ -939,10 +941,13 @@ hipError_t launch_adjoint_gather(const double* mu, double* lam, const Geom& g, h
   return hipGetLastError();
 }
 
-hipError_t launch_zero_pad_rows(double* buf, const Geom& g, hipStream_t s) {
+hipError_t launch_zero_pad_rows(void* buf, const Geom& g, int prec, hipStream_t s) {
   const long long n = (long long)Q * g.nx * (g.ny - g.ly);
-  hipLaunchKernelGGL(k_zero_pad_rows, dim3(grid_1d(n)), dim3(kThreads), 0, s, buf, g);
-  return hipGetLastError();
+  return by_precision(prec, [&](auto sv, auto) {
+    using S = decltype(sv);
+    hipLaunchKernelGGL(k_zero_pad_rows<S>, dim3(grid_1d(n)), dim3(kThreads), 0, s,
+                       static_cast<S*>(buf), g);
+  });
 }
 
 hipError_t launch_init_adjoint(const double* lam0, const double* rho, const double* ux,

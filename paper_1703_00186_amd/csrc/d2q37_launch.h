@@ -80,11 +80,12 @@ hipError_t launch_adjoint_step(const double* tape, const double* lam_in, double*
 // lambda read from a compact array (from_compact) or gathered from a padded
 // mu buffer (lambda_l(z) = mu_l(z + e_l)); the last step gathers into a
 // compact array.  Rows beyond the walls of a mu buffer must be zero
-// (launch_zero_pad_rows) or, for periodic y, refreshed halos.
+// (launch_zero_pad_rows: the padded rows outside [0, ly) of a padded buffer
+// of the given precision) or, for periodic y, refreshed halos.
 hipError_t launch_adjoint_mu(const double* tape, const double* in, bool from_compact, double* mu_out,
                              const Geom& g, const Phys& p, int regularize, hipStream_t s);
 hipError_t launch_adjoint_gather(const double* mu, double* lam, const Geom& g, hipStream_t s);
-hipError_t launch_zero_pad_rows(double* buf, const Geom& g, hipStream_t s);
+hipError_t launch_zero_pad_rows(void* buf, const Geom& g, int prec, hipStream_t s);
 hipError_t launch_init_adjoint(const double* lam0, const double* rho, const double* ux,
                                const double* uy, const double* T, double* drho, double* dux,
                                double* duy, double* dT, const Geom& g, hipStream_t s);

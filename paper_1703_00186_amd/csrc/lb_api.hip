@@ -254,9 +254,11 @@ int lb_init(const lb_lattice* lat, const lb_params* par, void* workspace, size_t
                                             observable_bytes(c->g));
   c->halos_valid = false;
   c->steps_since_check = 0;
-  // zero both buffers so that never-written padding (the y halo rows read by
-  // the wall rows' gather) holds finite values
-  hipError_t e = d2q37::launch_zero(ws, need, c->stream);
+  // Rows beyond the walls are never written by a step; the wall rows' gather
+  // reads them before bc replaces those populations.  Give them finite values
+  // (zero); every other element is written before it is read.
+  hipError_t e = d2q37::launch_zero_pad_rows(c->A, c->g, c->prec, c->stream);
+  if (e == hipSuccess) e = d2q37::launch_zero_pad_rows(c->B, c->g, c->prec, c->stream);
   if (e == hipSuccess)
     e = d2q37::launch_init_feq(c->A, rho0, ux0, uy0, T0, c->g, c->p, c->prec, c->stream);
   if (e != hipSuccess) {
@@ -506,8 +508,8 @@ int lb_adjoint_run(lb_ctx* ctx, int n, const double* tape, double* lambda, void*
     return LB_OK;
   }
   if (walls) {  // the gather reads zero beyond the walls
-    LB_HIP(d2q37::launch_zero_pad_rows(m0, g, ctx->stream), "adjoint_run pad rows");
-    LB_HIP(d2q37::launch_zero_pad_rows(m1, g, ctx->stream), "adjoint_run pad rows");
+    LB_HIP(d2q37::launch_zero_pad_rows(m0, g, LB_FP64, ctx->stream), "adjoint_run pad rows");
+    LB_HIP(d2q37::launch_zero_pad_rows(m1, g, LB_FP64, ctx->stream), "adjoint_run pad rows");
   }
   LB_HIP(d2q37::launch_adjoint_mu(tape + per * (n - 1), lambda, true, m0, g, ctx->p, reg,
                                   ctx->stream),

@@ -56,7 +56,7 @@ hipError_t launch_adjoint_mu(const double*, const double*, bool, double*, const 
 hipError_t launch_adjoint_gather(const double*, double*, const Geom&, hipStream_t) {
   return hipSuccess;
 }
-hipError_t launch_zero_pad_rows(double*, const Geom&, hipStream_t) { return hipSuccess; }
+hipError_t launch_zero_pad_rows(void*, const Geom&, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_init_adjoint(const double*, const double*, const double*, const double*,
                                const double*, double*, double*, double*, double*, const Geom&,
                                hipStream_t) {
