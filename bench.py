@@ -387,7 +387,13 @@ def _adjoint_workload(torch) -> dict:
                                       fields[3].grad.cpu().numpy(), seed=seed)
     rec = {"workload": "adjoint 512x512", "lattice": [lx, ly], "steps": n, "checkpoint_every": k,
            "KE": float(ke.detach().cpu()), "max_abs_grad": float(np.abs(g).max()),
-           "adjoint_vs_central_fd": fd, "forward_s": round(t_plain, 5),
+           "adjoint_vs_central_fd": fd,
+           # rounding noise of a central difference: ~16 ulps of KE over h,
+           # relative to max |dKE/da|; at h = 1e-6 it is the size of the
+           # difference itself (h = 1e-5 is below both noise and truncation)
+           "fd_noise_floor": {"%g" % h: float(16 * np.finfo(float).eps * float(ke.detach().cpu())
+                                              / h / np.abs(g).max()) for h in (1e-6, 1e-5)},
+           "forward_s": round(t_plain, 5),
            "forward_with_checkpoints_s": round(t1 - t0, 5), "backward_s": round(t2 - t1, 5),
            "backward_over_forward": round((t2 - t1) / t_plain, 3),
            "full_tape": {"tape_GB": round(n * 4 * lx * ly * 8 / 1e9, 3),
