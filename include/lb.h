@@ -205,8 +205,10 @@ int lb_run_observed(lb_ctx* ctx, int n, int every, double* series);
  * laid out like the state (aligned stores instead of the scatter's partial
  * ones); on lattices of 2^17 sites up to the cache size the steps are the
  * scatter kernel of lb_adjoint_step.  `workspace`: 256-byte aligned, at least
- * the size from lb_adjoint_workspace_bytes, previous contents irrelevant.
- * n = 0 leaves lambda unchanged.
+ * the size from lb_adjoint_workspace_bytes, previous contents irrelevant, and
+ * overlapping neither tape, lambda nor the context's own workspace.  n = 0
+ * leaves lambda unchanged.  Errors: LB_E_STATE (not FP64), LB_E_ARG (n < 0,
+ * NULL pointers), LB_E_WORKSPACE (size, alignment), LB_E_HIP.
  *
  * lb_init_adjoint: given lambda0 = dL/df^0 and the initial fields
  * (rho0, ux0, uy0, T0) the state was built from, writes dL/d(rho0, ux0, uy0,
