@@ -108,17 +108,19 @@ int lb_workspace_bytes(const lb_lattice* lat, const lb_params* par, size_t* byte
  * context.  The state is set to the equilibrium f_l = f^eq_l(rho0, u0, T0)
  * (Sec. 2: the run starts from an assignment of the populations at t = 0),
  * then the halos are refreshed.  rho0, ux0, uy0, T0: device FP64 [lx][ly].
- * Errors: LB_E_ARG (sizes < 6, tau <= 0.5, null pointers, reserved != 0),
- * LB_E_WORKSPACE, LB_E_HIP. */
+ * Errors: LB_E_ARG (sizes out of the limits of lb_lattice, tau <= 0.5,
+ * non-finite parameters, unknown enum values, null pointers, reserved != 0),
+ * LB_E_WORKSPACE (size, alignment), LB_E_HIP; *out is NULL on failure. */
 int lb_init(const lb_lattice* lat, const lb_params* par, void* workspace,
             size_t workspace_bytes, void* stream, const double* rho0,
             const double* ux0, const double* uy0, const double* T0,
             lb_ctx** out);
 
-/* Releases the host-side context (device memory belongs to the caller). */
+/* Releases the host-side context (device memory belongs to the caller).
+ * Enqueued work is not waited for.  NULL is accepted; always LB_OK. */
 int lb_free(lb_ctx* ctx);
 
-/* Changes the stream later work is enqueued on. */
+/* Changes the stream later work is enqueued on.  Errors: LB_E_ARG (NULL ctx). */
 int lb_set_stream(lb_ctx* ctx, void* stream);
 
 /* Replaces the physical parameters (tau, g, walls, regularize, kernel,
@@ -126,17 +128,22 @@ int lb_set_stream(lb_ctx* ctx, void* stream);
 int lb_set_params(lb_ctx* ctx, const lb_params* par);
 
 /* Advances the state by n >= 0 full steps (propagate -> bc -> collide),
- * with the fused kernel or the split kernels as par->kernel selects. */
+ * with the fused kernel or the split kernels as par->kernel selects.
+ * Errors: LB_E_ARG (NULL ctx, n < 0), LB_E_HIP, LB_E_NONFINITE (only with
+ * check_finite > 0: the scan found rho <= 0, T <= 0 or a non-finite value; the
+ * state is left as computed). */
 int lb_step(lb_ctx* ctx, int n);
 
 /* Eq. (2) of the current (post-collision) state: rho = sum f,
  * rho u = sum c f, 2 rho T = sum |c - u|^2 f, computed in FP64.  Outputs are
- * device FP64 [lx][ly]; any of them may be NULL. */
+ * device FP64 [lx][ly]; any of them may be NULL.  Errors: LB_E_ARG (NULL
+ * ctx), LB_E_HIP. */
 int lb_moments(lb_ctx* ctx, double* rho, double* ux, double* uy, double* T);
 
 /* Device copies of the state in compact form [37][lx][ly]: double for
  * LB_FP64, float g_l = f_l - w_l rho_ref for the FP32 modes.  set_state
- * refreshes the halos.  Used for checkpoints. */
+ * refreshes the halos.  Used for checkpoints.  Errors: LB_E_ARG (NULL
+ * pointers), LB_E_HIP. */
 int lb_get_state(lb_ctx* ctx, void* f);
 int lb_set_state(lb_ctx* ctx, const void* f);
 
@@ -172,11 +179,16 @@ int lb_set_scratch(lb_ctx* ctx, const void* f);
  * clamped to [0, 1] (the width of a linear temperature ramp).
  * lb_run_observed: n steps as lb_step; after every `every` steps the four
  * scalars are written to series + 4 * (k - 1) for the k-th sample (device
- * [n / every][4]); no host synchronisation. */
+ * [n / every][4]); no host synchronisation.  Errors: LB_E_ARG (NULL ctx,
+ * n < 0, every <= 0, series NULL when n >= every), LB_E_HIP, and those of
+ * lb_step. */
 int lb_observables(lb_ctx* ctx, double* profiles, double* scalars);
 int lb_run_observed(lb_ctx* ctx, int n, int every, double* series);
 
-/* Adjoint (LB_FP64 contexts only; LB_E_STATE otherwise).
+/* Adjoint (LB_FP64 contexts only; LB_E_STATE otherwise).  Besides that,
+ * every adjoint entry point returns LB_E_ARG for a NULL context or a NULL
+ * required pointer (the optional ones are named below) and LB_E_HIP for a
+ * launch failure; lb_adjoint_step also rejects lambda_in == lambda_out.
  *
  * lb_step_record: like lb_step(n) with the fused kernel, and also writes, for
  * each step j, the four pre-collision moments m = (rho, rho u_x, rho u_y,
