@@ -48,7 +48,16 @@ def setup(lx, ly, ybc="walls", regularize=1, g=(1e-3, -2e-3), steps=3, seed=5, l
     ("walls", 1, "column"), ("walls", 0, "column"), ("periodic", 1, "column"),
     ("periodic", 0, "column"), ("walls", 1, "soa"), ("periodic", 0, "soa")])
 def test_step_transpose(ybc, regularize, layout):
-    lx, ly = 24, 20
+    _transpose_check(24, 20, ybc, regularize, layout)
+
+
+@pytest.mark.parametrize("shape", [(6, 6), (7, 9)])
+def test_step_transpose_minimum_sizes(shape):
+    """Every column is an edge column and every row a wall row or next to one."""
+    _transpose_check(*shape, "walls", 1, "column")
+
+
+def _transpose_check(lx, ly, ybc, regularize, layout):
     lb, P, f, _ = setup(lx, ly, ybc, regularize, layout=layout)
     lb.set_state(torch.from_numpy(f))
     tape = lb.new_tape(1)
@@ -71,8 +80,8 @@ def test_step_transpose(ybc, regularize, layout):
 @pytest.mark.parametrize("ybc,regularize,layout", [
     ("walls", 1, "column"), ("walls", 0, "soa"), ("periodic", 1, "column"),
     ("periodic", 0, "soa")])
-@pytest.mark.parametrize("shape,n", [((37, 70), 1), ((37, 70), 7), ((130, 300), 3),
-                                     ((400, 400), 2), ((400, 400), 3)])
+@pytest.mark.parametrize("shape,n", [((6, 6), 4), ((7, 65), 3), ((37, 70), 1), ((37, 70), 7),
+                                     ((130, 300), 3), ((400, 400), 2), ((400, 400), 3)])
 def test_adjoint_run_equals_single_steps(ybc, regularize, layout, shape, n):
     """lb_adjoint_run gives lb_adjoint_step's result bit for bit: the gather
     form over padded buffers (ragged tiles of both tile shapes) and, at
