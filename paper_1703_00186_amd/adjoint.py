@@ -4,13 +4,13 @@
 the total kinetic energy KE = (1/2) sum rho |u|^2 after ``nsteps`` steps from
 f^0 = f^eq(rho0, u0, T0), as a differentiable scalar of the four initial
 fields.  Forward runs the fused step and keeps the state every
-``checkpoint_every`` steps.  Backward walks the segments last to first: it
-restores the segment's checkpoint, recomputes the segment while recording the
-four pre-collision moments of every site and step (lb_step_record), then
-applies the transposed steps (lb_adjoint_step) from the segment's end to its
-start (lb_adjoint_run: the transposed steps of a segment in one call, in
-gather form), and finally maps dL/df^0 to dL/d(rho0, u0, T0)
-(lb_init_adjoint).
+``checkpoint_every`` steps; the last segment is run with lb_step_record so
+that its tape (the four pre-collision moments of every site and step) is
+ready when the backward pass starts.  Backward walks the segments last to
+first: it restores the segment's checkpoint, recomputes the segment while
+recording its tape (not needed for the last one) and applies the segment's
+transposed steps from its end to its start in one lb_adjoint_run call; finally
+it maps dL/df^0 to dL/d(rho0, u0, T0) (lb_init_adjoint).
 With ``checkpoint_every=0`` the forward pass records the moments of every
 step instead (memory: 32 bytes per site and step, e.g. 1.7 GB for 200 steps of
 512 x 512, 107 GB for 100 steps of 8192 x 4096) and the backward pass only
@@ -41,15 +41,22 @@ class _KineticEnergy(torch.autograd.Function):
             ke, ctx.lam = lb.loss_ke(with_lambda=True)
             ctx.ckpts = None
             return ke[0].clone()
-        ctx.tape = ctx.lam = None
+        # checkpoints at the start of every segment but the last, whose tape
+        # is recorded right away (the backward pass starts there, so it needs
+        # no recomputation); dKE/df of the end state is kept too
+        ctx.tape = None
         ckpts = []
         done = 0
         while done < nsteps:
             n = min(every, nsteps - done)
-            ckpts.append((lb.get_state(), n))
-            lb.step(n)
+            if done + n < nsteps:
+                ckpts.append((lb.get_state(), n))
+                lb.step(n)
+            else:
+                ctx.last = (lb.new_tape(n), n)
+                lb.step_record(n, ctx.last[0])
             done += n
-        ke, _ = lb.loss_ke(with_lambda=False)
+        ke, ctx.lam = lb.loss_ke(with_lambda=True)
         ctx.ckpts = ckpts
         return ke[0].clone()
 
@@ -63,24 +70,19 @@ class _KineticEnergy(torch.autograd.Function):
             d = lb.init_adjoint(rho0, ux0, uy0, T0, lam)
             ctx.lb = ctx.tape = ctx.lam = None
             return d[0], d[1], d[2], d[3], None, None, None
-        lam = None
-        tape = None
-        if ctx.nsteps == 0:
-            lb.reinit(rho0, ux0, uy0, T0)
-            _, lam = lb.loss_ke(with_lambda=True)
-            lam.mul_(grad)
-        for state, n in reversed(ctx.ckpts):
-            if tape is None or tape.shape[0] < n:
-                tape = lb.new_tape(n)
-            lb.set_state(state)
-            lb.step_record(n, tape)
-            if lam is None:  # last segment: its end is the final state
-                _, lam = lb.loss_ke(with_lambda=True)
-                lam.mul_(grad)
-            lb.adjoint_run(tape, lam, n)
+        lam = ctx.lam.mul_(grad)
+        if ctx.nsteps > 0:
+            last_tape, n_last = ctx.last
+            lb.adjoint_run(last_tape, lam, n_last)
+            tape = last_tape
+            for state, n in reversed(ctx.ckpts):
+                if tape.shape[0] < n:  # the last segment may be the shorter one
+                    tape = lb.new_tape(n)
+                lb.set_state(state)
+                lb.step_record(n, tape)
+                lb.adjoint_run(tape, lam, n)
         d = lb.init_adjoint(rho0, ux0, uy0, T0, lam)
-        ctx.lb = None
-        ctx.ckpts = None
+        ctx.lb = ctx.ckpts = ctx.last = ctx.lam = None
         return d[0], d[1], d[2], d[3], None, None, None
 
 
