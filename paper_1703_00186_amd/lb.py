@@ -176,6 +176,7 @@ class LB:
         _check(self.lib.lb_set_stream(self.ctx, self._stream()))
 
     def field(self, a) -> torch.Tensor:
+        """An [lx, ly] field as a contiguous FP64 device tensor."""
         t = torch.as_tensor(a, dtype=torch.float64)
         if tuple(t.shape) != (self.lx, self.ly):
             raise ValueError("field must be [lx, ly]")
@@ -183,9 +184,11 @@ class LB:
 
     @property
     def state_dtype(self):
+        """torch dtype of the stored state: float64, or float32 for the FP32 forms."""
         return torch.float64 if self.precision == "fp64" else torch.float32
 
     def new_populations(self, dtype=None) -> torch.Tensor:
+        """An uninitialised [37, lx, ly] device tensor (state dtype by default)."""
         return torch.empty((Q, self.lx, self.ly), dtype=dtype or self.state_dtype,
                            device=self.device)
 
@@ -193,9 +196,11 @@ class LB:
     # (column) or [37, lx, ly] (SoA); lambda_view gives the [37, lx, ly] view
     @property
     def lambda_shape(self):
+        """Shape of an adjoint array in this lattice's layout."""
         return (self.lx, Q, self.ly) if self.layout == "column" else (Q, self.lx, self.ly)
 
     def new_lambda(self) -> torch.Tensor:
+        """An uninitialised FP64 adjoint array in this lattice's layout."""
         return torch.empty(self.lambda_shape, dtype=torch.float64, device=self.device)
 
     def lambda_view(self, lam: torch.Tensor) -> torch.Tensor:
@@ -232,6 +237,7 @@ class LB:
                                     *[_ptr(f) for f in fields], ctypes.byref(self.ctx)))
 
     def step(self, n: int = 1):
+        """Advances the state by n steps on the current stream (asynchronous)."""
         self._sync_stream()
         _check(self.lib.lb_step(self.ctx, int(n)))
 
@@ -259,6 +265,7 @@ class LB:
         return graph
 
     def moments(self):
+        """(rho, ux, uy, T) of the current state, Eq. (2), FP64 [lx, ly] each."""
         self._sync_stream()
         out = [torch.empty((self.lx, self.ly), dtype=torch.float64, device=self.device)
                for _ in range(4)]
@@ -282,6 +289,8 @@ class LB:
         return t.to(self.device).contiguous()
 
     def get_state(self, out=None) -> torch.Tensor:
+        """The state in compact [37, lx, ly] form, in the state dtype (FP32 forms:
+        the shifted values f - w rho_ref); `out` may be given to reuse a tensor."""
         self._sync_stream()
         if out is None:
             out = self.new_populations()
@@ -291,11 +300,13 @@ class LB:
         return out
 
     def set_state(self, f: torch.Tensor):
+        """Replaces the state by f (same form and dtype as get_state returns)."""
         self._sync_stream()
         f = self._state_arg(f, "state")
         _check(self.lib.lb_set_state(self.ctx, _ptr(f)))
 
     def populations(self) -> torch.Tensor:
+        """The populations f as FP64 [37, lx, ly], in every precision form."""
         self._sync_stream()
         out = self.new_populations(torch.float64)
         _check(self.lib.lb_get_populations(self.ctx, _ptr(out)))
@@ -303,28 +314,34 @@ class LB:
 
     # -- split stages ----------------------------------------------------------
     def halo(self):
+        """Refreshes the periodic halos of the state (split path)."""
         self._sync_stream()
         _check(self.lib.lb_halo(self.ctx))
 
     def propagate(self):
+        """Split path: scratch = propagate(state) (needs valid halos)."""
         self._sync_stream()
         _check(self.lib.lb_propagate(self.ctx))
 
     def bc(self):
+        """Split path: the thermal walls applied to the scratch buffer."""
         self._sync_stream()
         _check(self.lib.lb_bc(self.ctx))
 
     def collide(self):
+        """Split path: state = collide(scratch)."""
         self._sync_stream()
         _check(self.lib.lb_collide(self.ctx))
 
     def get_scratch(self) -> torch.Tensor:
+        """The scratch buffer in compact [37, lx, ly] form (state dtype)."""
         self._sync_stream()
         out = self.new_populations()
         _check(self.lib.lb_get_scratch(self.ctx, _ptr(out)))
         return out
 
     def set_scratch(self, f: torch.Tensor):
+        """Replaces the scratch buffer by f (compact form, state dtype)."""
         self._sync_stream()
         f = self._state_arg(f, "scratch")
         _check(self.lib.lb_set_scratch(self.ctx, _ptr(f)))
@@ -350,9 +367,12 @@ class LB:
 
     # -- adjoint -------------------------------------------------------------
     def new_tape(self, n: int) -> torch.Tensor:
+        """An uninitialised tape for n steps: FP64 [n, 4, lx, ly]."""
         return torch.empty((n, 4, self.lx, self.ly), dtype=torch.float64, device=self.device)
 
     def step_record(self, n: int, tape: torch.Tensor):
+        """n fused steps, writing the pre-collision moments (rho, j_x, j_y,
+        sum |c|^2 f) of step j to tape[j] (FP64 lattices only)."""
         self._sync_stream()
         if (not isinstance(tape, torch.Tensor) or tape.dim() != 4 or tape.shape[0] < n
                 or tuple(tape.shape[1:]) != (4, self.lx, self.ly)):
@@ -361,6 +381,8 @@ class LB:
         _check(self.lib.lb_step_record(self.ctx, int(n), _ptr(tape)))
 
     def loss_ke(self, with_lambda: bool = True):
+        """(KE [1], dKE/df or None) of the current state on the device; dKE/df
+        is an adjoint array in this lattice's layout."""
         self._sync_stream()
         ke = torch.empty(1, dtype=torch.float64, device=self.device)
         lam = self.new_lambda() if with_lambda else None
@@ -368,6 +390,8 @@ class LB:
         return ke, lam
 
     def adjoint_step(self, tape_j: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor):
+        """One transposed step: lam_out = J_j^T lam_in for the step whose
+        moments are tape_j (scatter form, lb_adjoint_step)."""
         self._expect(tape_j, (4, self.lx, self.ly), torch.float64, "tape_j")
         self._check_lambda(lam_in)
         self._check_lambda(lam_out)
@@ -394,6 +418,8 @@ class LB:
         return lam
 
     def init_adjoint(self, rho0, ux0, uy0, T0, lam0: torch.Tensor):
+        """dL/d(rho0, ux0, uy0, T0) of f^0 = f^eq(rho0, u0, T0) given lam0 = dL/df^0;
+        four FP64 [lx, ly] tensors."""
         self._check_lambda(lam0)
         self._sync_stream()
         fields = [self.field(a) for a in (rho0, ux0, uy0, T0)]
@@ -428,6 +454,8 @@ class LB:
         return meta
 
     def close(self):
+        """Frees the host-side context (the device workspace stays with this
+        object until it is dropped)."""
         if getattr(self, "ctx", None) and self.ctx.value:
             self.lib.lb_free(self.ctx)
             self.ctx = ctypes.c_void_p(0)
