@@ -495,6 +495,37 @@ def _production_workload(args, torch) -> dict:
     return rec
 
 
+def run_rt(args, torch) -> dict:
+    """A long Rayleigh-Taylor run on the headline lattice with the in-situ
+    observables recorded on the device (lb_run_observed) every `every`
+    steps: total mass, kinetic energy, sum rho T and the mixing-layer width,
+    plus a finiteness scan (check_finite) at the same interval."""
+    from paper_1703_00186_amd import workload
+    from paper_1703_00186_amd.lb import LB
+
+    lx, ly, n, every = args.lx, args.ly, args.rt_steps, args.rt_every
+    f = workload.rt_fields(lx, ly, seed=workload.config_seed(2))[:4]
+    lb = LB(lx, ly, *f, check_finite=every)
+    prof0, sc0 = lb.observables()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    series = lb.run_observed(n, every)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s = series.cpu().numpy()
+    sc0 = sc0.cpu().numpy()
+    rec = {"run": "Rayleigh-Taylor %dx%d, %d steps, observables every %d" % (lx, ly, n, every),
+           "MLUPS_with_observables": round(mlups(lx * ly * n, dt), 1),
+           "initial": {"mass": float(sc0[0]), "KE": float(sc0[1]), "width": float(sc0[3])},
+           "series": {"step": [every * (i + 1) for i in range(len(s))],
+                      "mass_rel_change": [float(v / sc0[0] - 1) for v in s[:, 0]],
+                      "KE": [float(v) for v in s[:, 1]],
+                      "width": [float(v) for v in s[:, 3]]}}
+    log("rt run: %.1f MLUPS, final width %.2f, KE %.3e" % (
+        rec["MLUPS_with_observables"], s[-1, 3], s[-1, 1]))
+    return rec
+
+
 def run_ablations(args, torch) -> list:
     """Variants of the step: memory layout, plain BGK vs Hermite-regularized
     collision (speed, and the smallest tau that stays finite), and the FP32
@@ -603,6 +634,10 @@ def main(argv=None) -> int:
                     choices=["parity", "fp32", "adjoint", "production"],
                     help="run these workloads (all four when none is named) and print one "
                          "JSON record each instead of the headline line")
+    ap.add_argument("--rt-run", action="store_true",
+                    help="a long Rayleigh-Taylor run with in-situ observables (one JSON record)")
+    ap.add_argument("--rt-steps", type=int, default=20000)
+    ap.add_argument("--rt-every", type=int, default=500)
     ap.add_argument("--ablations", action="store_true",
                     help="run the layout / collision / stability / FP32-shift ablations")
     ap.add_argument("--stability-steps", type=int, default=5000)
@@ -625,6 +660,9 @@ def main(argv=None) -> int:
     from paper_1703_00186_amd import workload
     from paper_1703_00186_amd.lb import LB
 
+    if args.rt_run:
+        print(json.dumps(run_rt(args, torch)), flush=True)
+        return 0
     if args.workloads is not None or args.ablations:
         for rec in (run_workloads if args.workloads is not None else run_ablations)(args, torch):
             print(json.dumps(rec), flush=True)
