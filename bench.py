@@ -115,17 +115,17 @@ def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 3) -> None:
 
 def field_errors(m, ref) -> dict:
     """Relative errors per field of (rho, ux, uy, T): rho and T as max|d| over
-    max|ref|; u as max|du| over max(max|u|, sqrt(min T)) (the flow or thermal
-    speed, whichever is larger; rho u is a cancelling sum of thermal-speed
-    terms)."""
+    max|ref|; u as max|du| over max|u| (the vector error over the largest
+    speed).  u_thermal: the same velocity error over the thermal speed
+    sqrt(min T), for reference only."""
     import numpy as np
     m = [np.asarray(a, dtype=np.float64) for a in m]
     r = [np.asarray(a, dtype=np.float64) for a in ref]
     du = np.hypot(m[1] - r[1], m[2] - r[2])
-    scale_u = max(float(np.hypot(r[1], r[2]).max()), float(np.sqrt(r[3].min())))
     return {"rho": float(np.abs(m[0] - r[0]).max() / np.abs(r[0]).max()),
-            "u": float(du.max() / scale_u),
-            "T": float(np.abs(m[3] - r[3]).max() / np.abs(r[3]).max())}
+            "u": float(du.max() / max(float(np.hypot(r[1], r[2]).max()), 1e-300)),
+            "T": float(np.abs(m[3] - r[3]).max() / np.abs(r[3]).max()),
+            "u_thermal": float(du.max() / float(np.sqrt(r[3].min())))}
 
 
 def host_moments(lb, torch):
@@ -213,10 +213,141 @@ def time_split_kernels(lb, steps: int, torch) -> dict:
     return {n: tot[n] / steps for n in names}
 
 
+# FP32 forms timed beside the FP64 headline: (key, precision, what it is)
+FP32_FORMS = (
+    ("fp32_shifted", "fp32c",
+     "FP32 storage of f - w rho_ref and FP32 collision about the site's rest Maxwellian "
+     "(FP64 for the collision invariants and the equilibrium coefficients)"),
+    ("fp32_storage_fp64_collide", "fp32s", "FP32 storage of f - w rho_ref, FP64 collision"),
+    ("fp32_shifted_f32sum", "fp32s_f32sum",
+     "ablation: FP32 storage, the FP64 collision's Hermite sums in FP32"),
+)
+FP32_WARMUP, FP32_TIMED, FP32_ERROR_STEPS = 20, 200, 2000
+
+
+def fp32_legs(lx: int, ly: int, fields, layout: str, fp64_mlups: float, torch) -> dict:
+    """Each FP32 form on the headline lattice: FP32_TIMED steps timed after
+    FP32_WARMUP warm-up steps (independent of --steps), then run on to
+    FP32_ERROR_STEPS steps and compared per field with the FP64 GPU run of as
+    many steps."""
+    from paper_1703_00186_amd.lb import LB
+
+    sites = lx * ly
+    lb = LB(lx, ly, *fields, layout=layout)
+    lb.step(FP32_ERROR_STEPS)
+    m64 = host_moments(lb, torch)
+    del lb
+    torch.cuda.empty_cache()
+    out = {}
+    for key, prec, what in FP32_FORMS:
+        lb32 = LB(lx, ly, *fields, precision=prec, layout=layout, kernel="fused")
+        lb32.step(FP32_WARMUP)
+        t32 = time_steps(lb32, FP32_TIMED, torch)
+        lb32.step(FP32_ERROR_STEPS - FP32_WARMUP - FP32_TIMED)
+        errs = field_errors(host_moments(lb32, torch), m64)
+        v32 = mlups(sites * FP32_TIMED, t32)
+        gbs = bytes_per_site("fp32") * sites / (t32 / FP32_TIMED) / 1e9
+        out[key] = {
+            "form": what, "precision": prec,
+            "MLUPS": round(v32, 2), "ms_per_step": round(t32 / FP32_TIMED * 1e3, 5),
+            "steps_timed": FP32_TIMED, "warmup": FP32_WARMUP,
+            "ratio_vs_fp64": round(v32 / fp64_mlups, 3),
+            "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "error_vs_fp64_gpu": {k: float("%.3g" % v) for k, v in errs.items()},
+            "error_after_steps": FP32_ERROR_STEPS}
+        fl = counted_fp32_mode_flops(prec)
+        if fl is not None:
+            rate = sites / (t32 / FP32_TIMED) / 1e12
+            out[key]["compute"] = {
+                "fp64_flop_per_site_counted": fl[0], "fp32_flop_per_site_counted": fl[1],
+                "fp64_TFLOPs": round(fl[0] * rate, 2),
+                "fp64_frac": round(fl[0] * rate / FP64_VECTOR_PEAK_TFLOPS, 4),
+                "fp32_TFLOPs": round(fl[1] * rate, 2),
+                "fp32_frac": round(fl[1] * rate / FP32_VECTOR_PEAK_TFLOPS, 4)}
+        log("bench: fused %s %.1f MLUPS (x%.2f), errors after %d steps %s" % (
+            prec, v32, v32 / fp64_mlups, FP32_ERROR_STEPS, errs))
+        del lb32
+        torch.cuda.empty_cache()
+    return out
+
+
+def production_leg(torch, steps: int = 200, warmup: int = 10, n_adj: int = 100,
+                   k: int = 20) -> dict:
+    """The production lattice, 8192 x 4096 (multimode RT): FP64 and FP32 step
+    speed and workspace, then the adjoint of the last n_adj FP64 steps with
+    checkpoints every k steps (backward cost over the plain forward run of the
+    same steps)."""
+    from paper_1703_00186_amd import workload
+    from paper_1703_00186_amd.lb import LB
+
+    lx, ly = 8192, 4096
+    sites = lx * ly
+    fields = workload.rt_fields(lx, ly, seed=workload.config_seed(5), mode="multimode")[:4]
+    rec = {"lattice": [lx, ly], "steps_timed": steps, "warmup": warmup}
+    for prec in ("fp32c", "fp32s", "fp64"):
+        torch.cuda.empty_cache()
+        lb = LB(lx, ly, *fields, precision=prec)
+        ws = int(lb.workspace.numel())
+        lb.step(warmup)
+        t = time_steps(lb, steps, torch)
+        v = mlups(sites * steps, t)
+        gbs = bytes_per_site("fp64" if prec == "fp64" else "fp32") * sites / (t / steps) / 1e9
+        rec[prec] = {"MLUPS": round(v, 1), "ms_per_step": round(t / steps * 1e3, 4),
+                     "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "workspace_bytes": ws}
+        log("bench: 8192x4096 %s %.1f MLUPS (%.1f GB/s)" % (prec, v, gbs))
+        if prec != "fp64":
+            del lb
+    # adjoint of the last n_adj steps (the schedule of adjoint.kinetic_energy:
+    # checkpoints at the start of every segment but the last, whose tape the
+    # forward pass records)
+    base = device_bytes_in_use(torch)
+    ckpts = []
+    tape = lb.new_tape(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(0, n_adj - k, k):
+        ckpts.append(lb.get_state())
+        lb.step(k)
+    lb.step_record(k, tape)
+    _, lam = lb.loss_ke(with_lambda=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lb.adjoint_run(tape, lam, k)
+    for ck in reversed(ckpts):
+        lb.set_state(ck)
+        lb.step_record(k, tape)
+        lb.adjoint_run(tape, lam, k)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    t_plain = n_adj * rec["fp64"]["ms_per_step"] / 1e3
+    rec["fp64"]["adjoint_last_steps"] = {
+        "steps": n_adj, "checkpoint_every": k,
+        "forward_with_checkpoints_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+        "backward_over_forward": round((t2 - t1) / t_plain, 3),
+        "checkpoints_tape_lambda_bytes": int(device_bytes_in_use(torch) - base),
+        "finite": bool(torch.isfinite(lam).all())}
+    rec["peak_device_bytes"] = int(torch.cuda.max_memory_allocated())
+    log("bench: 8192x4096 adjoint %s" % rec["fp64"]["adjoint_last_steps"])
+    del lb, ckpts, tape, lam
+    torch.cuda.empty_cache()
+    return rec
+
+
+# Host threads of the CPU legs: every core this process may run on, capped at
+# 16, the host-core share of one GPU on the MI355X nodes this runs on (their
+# affinity mask can show more cores than that share).
+CPU_THREAD_CAP = 16
+
+
+def cpu_threads() -> int:
+    return min(CPU_THREAD_CAP, len(os.sched_getaffinity(0)))
+
+
 def cpu_baseline(lx: int, ly: int, fields, steps: int) -> dict:
     import oracle
 
-    threads = min(16, len(os.sched_getaffinity(0)))
+    threads = cpu_threads()
     oracle.set_threads(threads)
     P = oracle.Params(tau=0.7, gx=0.0, gy=-1e-4, t_bottom=1.5, t_top=0.5)
     f = oracle.init_feq(*fields)
@@ -226,8 +357,9 @@ def cpu_baseline(lx: int, ly: int, fields, steps: int) -> dict:
     dt = time.perf_counter() - t0
     return {"value": round(mlups(lx * ly * steps, dt), 4), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "sample": "%d steps of the %dx%d FP64 RT lattice after 1 warm-up step (%.1f s), %s"
-                      % (steps, lx, ly, dt, cpu_model())}
+            "sample": "%d steps of the %dx%d FP64 RT lattice after 1 warm-up step (%.1f s), %s, "
+                      "%d threads (all affine cores, at most %d: one GPU's host-core share)"
+                      % (steps, lx, ly, dt, cpu_model(), threads, CPU_THREAD_CAP)}
 
 
 def cpu_model() -> str:
@@ -287,8 +419,8 @@ def _parity_workload(P, torch) -> dict:
 
 
 def _fp32_workload(args, P, torch) -> dict:
-    """4096 x 4096, FP32 shifted (both sum precisions) vs FP64 on the GPU,
-    plus FP32 shifted vs the oracle on 256 x 256."""
+    """4096 x 4096, the FP32 forms vs FP64 on the GPU, plus each FP32 form vs
+    the oracle on 256 x 256."""
     import oracle
     from paper_1703_00186_amd import workload
     from paper_1703_00186_amd.lb import LB
@@ -297,27 +429,28 @@ def _fp32_workload(args, P, torch) -> dict:
     f = workload.rt_fields(lx, ly, seed=workload.config_seed(3))[:4]
     rec = {"workload": "FP32 precision 4096x4096", "lattice": [lx, ly], "steps": n}
     ms = {}
-    for prec in ("fp64", "fp32s", "fp32s_f32sum"):
+    for prec in ("fp64", "fp32c", "fp32s", "fp32s_f32sum"):
         lb = LB(lx, ly, *f, precision=prec)
         t = time_steps(lb, n, torch)
         ms[prec] = host_moments(lb, torch)
         rec[prec] = {"MLUPS": round(mlups(lx * ly * n, t), 1)}
         del lb
         torch.cuda.empty_cache()
-    for prec in ("fp32s", "fp32s_f32sum"):
+    for prec in ("fp32c", "fp32s", "fp32s_f32sum"):
         rec[prec]["error_vs_fp64_gpu"] = field_errors(ms[prec], ms["fp64"])
         rec[prec]["ratio_vs_fp64"] = round(rec[prec]["MLUPS"] / rec["fp64"]["MLUPS"], 3)
     lxs = 256
     fs = workload.rt_fields(lxs, lxs, seed=workload.config_seed(3))[:4]
-    lb = LB(lxs, lxs, *fs, precision="fp32s")
-    lb.step(n)
     t0 = time.perf_counter()
     ref = oracle.moments(oracle.run(oracle.init_feq(*fs), P, n))
     t_or = time.perf_counter() - t0
-    rec["fp32s"]["error_vs_oracle_256x256"] = field_errors(host_moments(lb, torch), ref)
+    for prec in ("fp32c", "fp32s", "fp32s_f32sum"):
+        lb = LB(lxs, lxs, *fs, precision=prec)
+        lb.step(n)
+        rec[prec]["error_vs_oracle_256x256"] = field_errors(host_moments(lb, torch), ref)
+        del lb
     rec["oracle_256x256"] = {"MLUPS": round(mlups(lxs * lxs * n, t_or), 2),
                              "seconds": round(t_or, 2), "threads": oracle.get_threads()}
-    del lb
     torch.cuda.empty_cache()
     log("workloads: %s" % rec)
     return rec
@@ -539,7 +672,7 @@ def run_ablations(args, torch) -> list:
     f = workload.rt_fields(lx, ly, seed=workload.config_seed(2))[:4]
     speed = {}
     for layout in ("soa", "column"):
-        for prec in ("fp64", "fp32s"):
+        for prec in ("fp64", "fp32c", "fp32s"):
             for reg in (1, 0):
                 lb = LB(lx, ly, *f, precision=prec, layout=layout, regularize=reg)
                 lb.step(20)
@@ -583,7 +716,7 @@ def run_ablations(args, torch) -> list:
     m64 = host_moments(lb, torch)
     del lb
     shift = {}
-    for prec in ("fp32s", "fp32s_f32sum"):
+    for prec in ("fp32c", "fp32s", "fp32s_f32sum"):
         for rho_ref in (0.0, 1.0):
             lb = LB(al, al, *fa, precision=prec, rho_ref=rho_ref)
             lb.step(n)
@@ -601,7 +734,7 @@ def cpu_optimised(lx: int, ly: int, fields, steps: int = 40) -> dict:
     import cpu_step
     import oracle
 
-    threads = min(16, len(os.sched_getaffinity(0)))
+    threads = cpu_threads()
     cpu_step.set_threads(threads)
     lat = cpu_step.CpuLattice(lx, ly, oracle.init_feq(*fields))
     lat.step(2)
@@ -715,43 +848,16 @@ def main(argv=None) -> int:
         out["split_fp64"]["collide"]["GB/s"] = round(bytes_per_site() * sites / sp["collide"] / 1e9, 1)
         out["split_fp64"]["step"] = {"ms": round(tot * 1e3, 5), "MLUPS": round(mlups(sites, tot), 1)}
         log("bench: split FP64 %s" % json.dumps(out["split_fp64"]))
-        # the split path advanced the FP64 lattice: rerun it for the comparison
+        # the split path advanced the FP64 lattice: reinit it for the adjoint
         lb.reinit(*fields)
         lb.set_params(kernel="fused")
-        lb.step(args.warmup + args.steps)
-        m64 = host_moments(lb, torch)
+        lb.step(args.warmup)
         out["adjoint_fp64"] = time_adjoint(lb, args.adjoint_steps, torch)
         log("bench: adjoint %s" % json.dumps(out["adjoint_fp64"]))
         del lb
         torch.cuda.empty_cache()
-        for key, prec in (("fp32_shifted", "fp32s"), ("fp32_shifted_f32sum", "fp32s_f32sum")):
-            lb32 = LB(lx, ly, *fields, precision=prec, layout=args.layout, kernel="fused")
-            lb32.step(args.warmup)
-            t32 = time_steps(lb32, args.steps, torch)
-            v32 = mlups(sites * args.steps, t32)
-            errs = field_errors(host_moments(lb32, torch), m64)
-            out[key] = {
-                "MLUPS": round(v32, 2), "ms_per_step": round(t32 / args.steps * 1e3, 5),
-                "ratio_vs_fp64": round(v32 / value, 3),
-                "GB/s": round(bytes_per_site("fp32") * sites / (t32 / args.steps) / 1e9, 1),
-                "error_vs_fp64_gpu": {k: float("%.3g" % v) for k, v in errs.items()},
-                "error_after_steps": args.warmup + args.steps}
-            if prec == "fp32s_f32sum":
-                out[key]["note"] = ("ablation: Hermite sums in FP32; its error grows past 1e-5 "
-                                    "within ~500 steps, so the FP32 form that meets 1e-5 keeps "
-                                    "the sums in FP64 (fp32_shifted)")
-            fl = counted_fp32_mode_flops(prec)
-            if fl is not None:
-                rate = sites / (t32 / args.steps) / 1e12
-                out[key]["compute"] = {
-                    "fp64_flop_per_site_counted": fl[0], "fp32_flop_per_site_counted": fl[1],
-                    "fp64_TFLOPs": round(fl[0] * rate, 2),
-                    "fp64_frac": round(fl[0] * rate / FP64_VECTOR_PEAK_TFLOPS, 4),
-                    "fp32_TFLOPs": round(fl[1] * rate, 2),
-                    "fp32_frac": round(fl[1] * rate / FP32_VECTOR_PEAK_TFLOPS, 4)}
-            log("bench: fused %s %.1f MLUPS (x%.2f), errors %s" % (prec, v32, v32 / value, errs))
-            del lb32
-            torch.cuda.empty_cache()
+        out.update(fp32_legs(lx, ly, fields, args.layout, value, torch))
+        out["production_8192x4096"] = production_leg(torch)
     if not args.no_extras:
         # launch-bound small lattice: eager launches vs one graph of 100 steps
         sl, sh = 256, 128

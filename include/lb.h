@@ -52,12 +52,24 @@ extern "C" {
 #define LB_E_NONFINITE (-5) /* check_finite found rho<=0, T<=0 or NaN/Inf  */
 
 /* lb_lattice.precision.  The FP32 modes store g_l = f_l - w_l rho_ref in FP32
- * (half the HBM traffic of FP64); moments, equilibrium coefficients,
- * relaxation and bc are FP64 in every mode. */
-#define LB_FP64 0                /* FP64 storage, FP64 sums                     */
-#define LB_FP32_SHIFTED 1        /* FP32 storage, FP64 Hermite sums (projection */
-                                 /* and reconstruction)                         */
-#define LB_FP32_SHIFTED_F32SUM 2 /* FP32 storage, FP32 Hermite sums             */
+ * (half the HBM traffic of FP64) and differ in the arithmetic of the
+ * collision; bc and the moments of lb_moments are FP64 in every mode.
+ *  LB_FP32_SHIFTED: FP32 storage, FP64 collision (every sum and product of
+ *    the collision in FP64, one rounding to FP32 on store).
+ *  LB_FP32_SHIFTED_F32SUM: FP32 storage, the FP64 collision's Hermite sums in
+ *    FP32 (an ablation: its error grows past 1e-5 within a few hundred steps
+ *    of the Rayleigh-Taylor lattice).
+ *  LB_FP32_COLLIDE: FP32 storage, FP32 collision.  The Hermite projection and
+ *    reconstruction run in FP32 on the deviation of the populations from the
+ *    site's rest Maxwellian; FP64 is kept for the sums of the collision
+ *    invariants (mass, momentum, energy), the reference Maxwellian and the
+ *    equilibrium's Hermite coefficients (Sec. 2: the collision is a
+ *    relaxation towards that equilibrium, projected on Hermite polynomials). */
+#define LB_FP64 0                /* FP64 storage, FP64 collision           */
+#define LB_FP32_SHIFTED 1        /* FP32 storage, FP64 collision           */
+#define LB_FP32_SHIFTED_F32SUM 2 /* FP32 storage, FP32 Hermite sums        */
+#define LB_FP32_COLLIDE 3        /* FP32 storage, FP32 collision about the */
+                                 /* rest Maxwellian, FP64 invariants       */
 /* lb_lattice.ybc */
 #define LB_Y_WALLS 0    /* thermal walls below row 0 and above row ly-1 */
 #define LB_Y_PERIODIC 1 /* periodic y (no walls), for tests             */
@@ -73,7 +85,7 @@ typedef struct lb_lattice {
   int32_t lx;        /* physical sites along x (periodic), 6 .. 2^22    */
   int32_t ly;        /* physical sites along y (walls), 6 .. 2^24;      */
                      /* lx * ly <= 2^30                                 */
-  int32_t precision; /* LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM */
+  int32_t precision; /* LB_FP64 or one of the FP32 modes above       */
   int32_t ybc;       /* LB_Y_WALLS or LB_Y_PERIODIC                     */
   int32_t layout;    /* LB_LAYOUT_SOA or LB_LAYOUT_COLUMN               */
   int32_t reserved;  /* must be 0                                       */
@@ -95,7 +107,8 @@ typedef struct lb_params {
 typedef struct lb_ctx lb_ctx;
 
 const char* lb_last_error(void);
-/* Interface version: 3 (adjoint arrays in the lattice's layout; lb_adjoint_run). */
+/* Interface version: 4 (3: adjoint arrays in the lattice's layout and
+ * lb_adjoint_run; 4: precision LB_FP32_COLLIDE). */
 int lb_version(void);
 
 /* Bytes of device workspace lb_init needs for this lattice (two padded

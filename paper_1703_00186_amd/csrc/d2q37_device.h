@@ -24,6 +24,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "d2q37_constants.h"
 
 namespace d2q37 {
@@ -109,9 +111,10 @@ __device__ __forceinline__ void project(const A (&f)[Q], A (&a)[5][5]) {
 }
 
 // ---------------------------------------------------------------------------
-// reconstruct: f_l = w_l sum_pq b_pq He_p(c_lx) He_q(c_ly) / (p! q!).
+// reconstruct: f_l = w_l sum_pq b_pq He_p(c_lx) He_q(c_ly) / (p! q!), over the
+// Hermite orders p + q >= kMinOrder (the lower ones are left out).
 // ---------------------------------------------------------------------------
-template <class A>
+template <class A, int kMinOrder = 0>
 __device__ __forceinline__ void reconstruct(const A (&b)[5][5], A (&f)[Q]) {
 #pragma unroll
   for (int ex = 3; ex >= -3; --ex) {
@@ -123,7 +126,7 @@ __device__ __forceinline__ void reconstruct(const A (&b)[5][5], A (&f)[Q]) {
 #pragma unroll
       for (int p = 0; p + q < 5; ++p) {
         const double hp = hef(ex, p);
-        if (hp == 0.0) continue;
+        if (hp == 0.0 || p + q < kMinOrder) continue;
         if (hp == 1.0)
           s += b[p][q];
         else
@@ -327,6 +330,171 @@ __device__ __forceinline__ Tape4 collide_site(A (&f)[Q], const Phys& P) {
     for (int l = 0; l < Q; ++l) f[l] = keep * f[l] + om * feq[l];
   }
   return t;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 collision relative to a local reference (the FP32-arithmetic form).
+//
+// FP32 rounding is relative to the size of the numbers summed.  The
+// populations of a site lie close to its rest Maxwellian
+//   R_l = w_l rho [1 + th_R (|c_l|^2 - 2)/2 + th_R^2 (|c_l|^4 - 8|c_l|^2 + 8)/8]
+// (f^eq at u = 0 and temperature 1 + th_R, Eq. (2) moments exact), so the
+// non-conserved part of the collision is computed in FP32 on n_l = f_l - R_l,
+// small wherever the flow is slow and near equilibrium, while the collision
+// invariants are summed in FP64:
+//   1. FP64 sums of the stored values: mass rho, momentum j, energy
+//      E = sum |c|^2 f; th_R = E / (2 rho) - 1, so n carries no mass and no
+//      energy and its momentum is j;
+//   2. R_l - w_l rho_ref per weight family (|e_l|^2 fixes w_l and |c_l|^2),
+//      in FP64, kept as an unevaluated FP32 pair hi + lo;
+//   3. n_l = (g_l - hi) - lo in FP32 (the first difference is exact or off
+//      by half an ulp of n);
+//   4. the Hermite coefficients of n in FP32 (the FP32-accumulated moments),
+//      with a_00 = 0, a_10 = j_x, a_01 = j_y and a_20 + a_02 = 0 taken from
+//      step 1 instead;
+//   5. the forced equilibrium coefficients in FP64 at rho, u = j / rho,
+//      th = th_R - |u|^2 / 2 (Hermite orders up to four, where cancellation
+//      against the reference needs the digits); d_pq = a^eq_pq - a^R_pq
+//      rounded to FP32, with a^R_00 = rho, a^R_20 = a^R_02 = rho th_R,
+//      a^R_40 = a^R_04 = 3 rho th_R^2, a^R_22 = rho th_R^2, all others 0;
+//   6. the relaxed deviation b_pq = (1 - 1/tau) a^n_pq + d_pq / tau
+//      (regularized) reconstructed in FP32 as r_l; plain BGK relaxes n_l
+//      itself and adds the reconstruction of d / tau;
+//   7. g'_l = hi + (lo + r_l): one FP32 rounding of the stored value.
+// g holds f_l - w_l rho_ref in FP32 on entry and on return.
+// ---------------------------------------------------------------------------
+constexpr int kFamilies = 8;
+// weight family of hop l, numbered by |e_l|^2 = 0, 1, 2, 4, 5, 8, 9, 10
+__host__ __device__ constexpr int family_of(int l) {
+  return (EX[l] * EX[l] + EY[l] * EY[l]) == 0    ? 0
+         : (EX[l] * EX[l] + EY[l] * EY[l]) == 1 ? 1
+         : (EX[l] * EX[l] + EY[l] * EY[l]) == 2 ? 2
+         : (EX[l] * EX[l] + EY[l] * EY[l]) == 4 ? 3
+         : (EX[l] * EX[l] + EY[l] * EY[l]) == 5 ? 4
+         : (EX[l] * EX[l] + EY[l] * EY[l]) == 8 ? 5
+         : (EX[l] * EX[l] + EY[l] * EY[l]) == 9 ? 6
+                                                 : 7;
+}
+constexpr int kFamilyE2[kFamilies] = {0, 1, 2, 4, 5, 8, 9, 10};
+// a hop of each family (for its weight)
+constexpr int kFamilyLabel[kFamilies] = {18, 17, 10, 16, 9, 3, 15, 8};
+
+template <bool kRegularize>
+__device__ __forceinline__ void collide_site_ref(float (&g)[Q], const Phys& P) {
+  // 1. collision invariants in FP64: per-family, per-e_x and per-e_y sums
+  double sf[kFamilies], sx[7], sy[7];
+#pragma unroll
+  for (int k = 0; k < kFamilies; ++k) sf[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) sx[k] = sy[k] = 0.0;
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    const double v = double(g[l]);
+    sf[family_of(l)] += v;
+    if (EX[l] != 0) sx[EX[l] + 3] += v;
+    if (EY[l] != 0) sy[EY[l] + 3] += v;
+  }
+  double s0 = 0.0, s2 = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+  for (int k = 0; k < kFamilies; ++k) {
+    s0 += sf[k];
+    s2 += double(kFamilyE2[k]) * sf[k];
+  }
+#pragma unroll
+  for (int e = 1; e <= 3; ++e) {
+    jx += double(e) * (sx[3 + e] - sx[3 - e]);
+    jy += double(e) * (sy[3 + e] - sy[3 - e]);
+  }
+  // the shift w rho_ref adds rho_ref to the mass and 2 rho_ref to the energy
+  const double rho = P.rho_ref + s0;
+  const double inv_rho = 1.0 / rho;
+  const double th_r = 0.5 * (R * R * s2 + 2.0 * P.rho_ref) * inv_rho - 1.0;
+  jx *= R;
+  jy *= R;
+  // 2. reference per family: w (R/w - rho_ref) as hi + lo
+  float hi[kFamilies], lo[kFamilies];
+#pragma unroll
+  for (int k = 0; k < kFamilies; ++k) {
+    const double x2 = R * R * double(kFamilyE2[k]);
+    const double c1 = 0.5 * (x2 - 2.0), c2 = 0.125 * (x2 * x2 - 8.0 * x2 + 8.0);
+    const double v = W[kFamilyLabel[k]] * (rho * (1.0 + th_r * (c1 + c2 * th_r)) - P.rho_ref);
+    hi[k] = float(v);
+    lo[k] = float(v - double(hi[k]));
+  }
+  // 3. deviation from the reference
+  float n[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) n[l] = (g[l] - hi[family_of(l)]) - lo[family_of(l)];
+  // 4. FP32 Hermite coefficients of n
+  float an[5][5];
+  project<float>(n, an);
+  // 5. forced equilibrium minus the reference and the relaxed deviation, in
+  // FP64, rounded once to FP32.  The invariants come from step 1: n has no
+  // mass, momentum j and a_20 + a_02 = 0.
+  const double ux = jx * inv_rho, uy = jy * inv_rho;
+  const double th = th_r - 0.5 * (ux * ux + uy * uy);
+  double aeq[5][5];
+  equilibrium_coeffs(rho, ux + P.tau_gx, uy + P.tau_gy, th + P.dtheta, aeq);
+  const double th2 = th_r * th_r;
+  const double aR20 = rho * th_r, aR40 = 3.0 * rho * th2, aR22 = rho * th2;
+  const double om = P.omega, keep = 1.0 - P.omega;
+  const double half_diff = 0.5 * (double(an[2][0]) - double(an[0][2]));
+  float b[5][5];
+#pragma unroll
+  for (int p = 0; p < 5; ++p)
+#pragma unroll
+    for (int q = 0; q + p < 5; ++q) {
+      double ar = 0.0, a = double(an[p][q]);
+      if ((p == 2 && q == 0) || (p == 0 && q == 2)) ar = aR20;
+      if ((p == 4 && q == 0) || (p == 0 && q == 4)) ar = aR40;
+      if (p == 2 && q == 2) ar = aR22;
+      if (p == 1 && q == 0) a = jx;
+      if (p == 0 && q == 1) a = jy;
+      if (p == 2 && q == 0) a = half_diff;
+      if (p == 0 && q == 2) a = -half_diff;
+      b[p][q] = float(kRegularize ? keep * a + om * (aeq[p][q] - ar) : om * (aeq[p][q] - ar));
+    }
+  b[0][0] = 0.0f;  // a^eq_00 = rho = a^R_00: collision conserves mass
+  // 6. reconstruct the deviation in FP32; the first-order (momentum) terms
+  // on their own, not rounded inside the column sums of the larger
+  // higher-order terms
+  float r[Q];
+  reconstruct<float, 2>(b, r);
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    float r1 = 0.0f;
+    if (EX[l] != 0) r1 += float(W[l] * R * EX[l]) * b[1][0];
+    if (EY[l] != 0) r1 += float(W[l] * R * EY[l]) * b[0][1];
+    r[l] = kRegularize ? r1 + r[l] : float(keep) * n[l] + (r1 + r[l]);
+  }
+  // 7. back to stored values
+#pragma unroll
+  for (int l = 0; l < Q; ++l) g[l] = hi[family_of(l)] + (lo[family_of(l)] + r[l]);
+}
+
+// Collision dispatch on the accumulation type: double or float run
+// collide_site in that type; F32Ref (populations in float registers) runs
+// collide_site_ref.  The tape is produced by the FP64 form only.
+struct F32Ref {};
+template <class A>
+struct reg_of {
+  using type = A;
+};
+template <>
+struct reg_of<F32Ref> {
+  using type = float;
+};
+template <class A>
+using reg_t = typename reg_of<A>::type;
+
+template <class A, bool kRegularize>
+__device__ __forceinline__ Tape4 collide(reg_t<A> (&f)[Q], const Phys& P) {
+  if constexpr (std::is_same<A, F32Ref>::value) {
+    collide_site_ref<kRegularize>(f, P);
+    return Tape4{0.0, 0.0, 0.0, 0.0};
+  } else {
+    return collide_site<A, kRegularize>(f, P);
+  }
 }
 
 }  // namespace d2q37

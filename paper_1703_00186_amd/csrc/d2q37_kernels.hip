@@ -114,10 +114,11 @@ __global__ __launch_bounds__(kThreads) void k_fused(const S* __restrict__ src,
   int x, y;
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
   const long long site = padded<S>(g, x + HX, y + g.hy);
-  A f[Q];
-  gather<S, A>(src, g, site, f);
-  if (on_wall_rows(g, y)) wall_site<A>(f, y, g.ly, P.th_bottom, P.th_top, P.rho_ref);
-  const Tape4 m = collide_site<A, kReg>(f, P);
+  using V = reg_t<A>;
+  V f[Q];
+  gather<S, V>(src, g, site, f);
+  if (on_wall_rows(g, y)) wall_site<V>(f, y, g.ly, P.th_bottom, P.th_top, P.rho_ref);
+  const Tape4 m = collide<A, kReg>(f, P);
   if (kTape) {
     const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
     tape[s] = m.rho;
@@ -125,9 +126,9 @@ __global__ __launch_bounds__(kThreads) void k_fused(const S* __restrict__ src,
     tape[2 * S2 + s] = m.jy;
     tape[3 * S2 + s] = m.e;
   }
-  store_site<S, A>(dst, g, site, f);
-  if (x < HX) store_site<S, A>(dst, g, site + (long long)g.lx * g.cs, f);
-  if (x >= g.lx - HX) store_site<S, A>(dst, g, site - (long long)g.lx * g.cs, f);
+  store_site<S, V>(dst, g, site, f);
+  if (x < HX) store_site<S, V>(dst, g, site + (long long)g.lx * g.cs, f);
+  if (x >= g.lx - HX) store_site<S, V>(dst, g, site - (long long)g.lx * g.cs, f);
 }
 
 template <class S>
@@ -149,10 +150,11 @@ __global__ __launch_bounds__(kThreads) void k_collide(const S* __restrict__ src,
   int x, y;
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
   const long long site = padded<S>(g, x + HX, y + g.hy);
-  A f[Q];
-  load_site<S, A>(src, g, site, f);
-  collide_site<A, kReg>(f, P);
-  store_site<S, A>(dst, g, site, f);
+  using V = reg_t<A>;
+  V f[Q];
+  load_site<S, V>(src, g, site, f);
+  collide<A, kReg>(f, P);
+  store_site<S, V>(dst, g, site, f);
 }
 
 // bc on the six wall rows, in place; one thread per (x, wall row).
@@ -697,8 +699,10 @@ unsigned grid_1d(long long n) { return unsigned((n + kThreads - 1) / kThreads); 
 // ---------------------------------------------------------------------------
 
 // Calls fn(S{}, A{}) with the storage type S and the arithmetic type A of a
-// precision mode: FP64 storage and sums; FP32 storage with FP64 sums; FP32
-// storage with FP32 sums.  Moments, equilibrium coefficients, relaxation and
+// precision mode -> (storage type, accumulation type): FP64 storage and
+// collision; FP32 storage with the FP64 collision; FP32 storage with the
+// plain FP32 collision; FP32 storage with the FP32 collision about the local
+// rest Maxwellian (collide_site_ref).  Moments, equilibrium coefficients and
 // bc are FP64 in every mode.
 template <class Fn>
 hipError_t by_precision(int prec, Fn fn) {
@@ -706,8 +710,10 @@ hipError_t by_precision(int prec, Fn fn) {
     fn(double{}, double{});
   else if (prec == kF32Shifted)
     fn(float{}, double{});
-  else
+  else if (prec == kF32ShiftedF32Sum)
     fn(float{}, float{});
+  else
+    fn(float{}, F32Ref{});
   return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ int check_lattice(const lb_lattice* lat) {
       (long long)lat->lx * lat->ly > (1LL << 30))
     return fail(LB_E_ARG, "lattice too large (lx <= 2^22, ly <= 2^24, lx*ly <= 2^30)%s");
   if (lat->precision != LB_FP64 && lat->precision != LB_FP32_SHIFTED &&
-      lat->precision != LB_FP32_SHIFTED_F32SUM)
+      lat->precision != LB_FP32_SHIFTED_F32SUM && lat->precision != LB_FP32_COLLIDE)
     return fail(LB_E_ARG, "unknown precision%s");
   if (lat->ybc != LB_Y_WALLS && lat->ybc != LB_Y_PERIODIC) return fail(LB_E_ARG, "unknown ybc%s");
   if (lat->layout != LB_LAYOUT_SOA && lat->layout != LB_LAYOUT_COLUMN)
@@ -208,7 +208,7 @@ extern "C" {
 
 const char* lb_last_error(void) { return g_error.c_str(); }
 
-int lb_version(void) { return 3; }
+int lb_version(void) { return 4; }
 
 int lb_workspace_bytes(const lb_lattice* lat, const lb_params* par, size_t* bytes) {
   int rc = check_lattice(lat);

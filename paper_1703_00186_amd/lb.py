@@ -19,7 +19,11 @@ from . import build as _build
 
 Q = 37
 
-LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM = 0, 1, 2
+LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM, LB_FP32_COLLIDE = 0, 1, 2, 3
+# precision names: FP64; FP32 storage with the FP64 collision; with FP32
+# Hermite sums (ablation); with the FP32 collision about the rest Maxwellian
+PRECISIONS = {"fp64": LB_FP64, "fp32s": LB_FP32_SHIFTED, "fp32s_f32sum": LB_FP32_SHIFTED_F32SUM,
+              "fp32c": LB_FP32_COLLIDE}
 LB_Y_WALLS, LB_Y_PERIODIC = 0, 1
 LB_LAYOUT_SOA, LB_LAYOUT_COLUMN = 0, 1
 LB_KERNEL_FUSED, LB_KERNEL_SPLIT = 0, 1
@@ -133,7 +137,7 @@ def make_params(tau=0.7, g=(0.0, -1e-4), t_bottom=1.5, t_top=0.5, rho_ref=1.0, r
 
 
 def make_lattice(lx, ly, precision="fp64", ybc="walls", layout="column") -> Lattice:
-    p = {"fp64": LB_FP64, "fp32s": LB_FP32_SHIFTED, "fp32s_f32sum": LB_FP32_SHIFTED_F32SUM}[precision]
+    p = PRECISIONS[precision]
     y = {"walls": LB_Y_WALLS, "periodic": LB_Y_PERIODIC}[ybc]
     lay = {"soa": LB_LAYOUT_SOA, "column": LB_LAYOUT_COLUMN}[layout]
     return Lattice(int(lx), int(ly), p, y, lay, 0)

@@ -136,7 +136,7 @@ void check_context(int precision, int layout, int kernel, int ybc) {
 }  // namespace
 
 int main() {
-  EXPECT(lb_version() == 3);
+  EXPECT(lb_version() == 4);
   lb_lattice lat = {64, 48, LB_FP64, LB_Y_WALLS, LB_LAYOUT_COLUMN, 0};
   lb_params par = {0.7, 0.0, -1e-4, 1.5, 0.5, 1.0, 1, LB_KERNEL_FUSED, 0, 0};
   size_t need = 0;
@@ -172,7 +172,7 @@ int main() {
   lb_lattice big = {1 << 16, 1 << 14, LB_FP64, LB_Y_WALLS, LB_LAYOUT_COLUMN, 0};
   EXPECT(lb_workspace_bytes(&big, &par, &need) == LB_OK);
 
-  for (int prec : {LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM})
+  for (int prec : {LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM, LB_FP32_COLLIDE})
     for (int layout : {LB_LAYOUT_SOA, LB_LAYOUT_COLUMN})
       for (int kernel : {LB_KERNEL_FUSED, LB_KERNEL_SPLIT})
         for (int ybc : {LB_Y_WALLS, LB_Y_PERIODIC}) check_context(prec, layout, kernel, ybc);

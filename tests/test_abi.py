@@ -117,7 +117,7 @@ def test_largest_lattice_is_accepted(lib):
 
 
 def test_version(lib):
-    assert lib.lb_version() == 3
+    assert lib.lb_version() == 4
 
 
 def test_binding_refuses_to_run_without_the_hip_library(monkeypatch, tmp_path):

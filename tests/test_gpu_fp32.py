@@ -1,10 +1,17 @@
-"""FP32 "shifted populations" form on the GPU.
+"""FP32 "shifted populations" forms on the GPU.
 
-Storage and sums in FP32 of g_l = f_l - w_l rho_ref (rho_ref = 1), with the
-equilibrium coefficients and the relaxation in FP64.  Checked per field
-(rho, u, T; the metric of tests/helpers.py) against the FP64 oracle on a
-256 x 256 Rayleigh-Taylor rerun over 2000 steps, and against the FP64 GPU
-step on the 4096 x 4096 lattice over 2000 steps: both within 1e-5.
+Every FP32 mode stores g_l = f_l - w_l rho_ref in FP32 (rho_ref = 1 unless a
+test says otherwise):
+  fp32c         FP32 collision about the site's rest Maxwellian, FP64 only
+                for the collision invariants and the equilibrium coefficients
+                (the FP32-arithmetic form);
+  fp32s         the FP64 collision on FP32 storage;
+  fp32s_f32sum  the FP64 collision's Hermite sums in FP32 (ablation).
+Checked per field (rho, u, T; u as max|du| / max|u|, tests/helpers.py)
+against the FP64 oracle on a 256 x 256 Rayleigh-Taylor rerun over 2000 steps
+and against the FP64 GPU step on the 4096 x 4096 lattice over 2000 steps:
+both within 1e-5 for fp32c and fp32s.  The ablation is held to the bound its
+measured error states.
 """
 
 import numpy as np
@@ -26,14 +33,17 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def oparams():
-    return oracle.Params(tau=0.7, gx=0.0, gy=-1e-4, t_bottom=1.5, t_top=0.5)
+def oparams(**kw):
+    p = dict(tau=0.7, gx=0.0, gy=-1e-4, t_bottom=1.5, t_top=0.5)
+    p.update(kw)
+    return oracle.Params(**p)
 
 
-def test_fp32_state_is_shifted_and_propagate_exact():
+@pytest.mark.parametrize("precision", ["fp32s", "fp32c"])
+def test_fp32_state_is_shifted_and_propagate_exact(precision):
     lx, ly = 40, 70
     rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=1)
-    lb = LB(lx, ly, rho, ux, uy, T, precision="fp32s")
+    lb = LB(lx, ly, rho, ux, uy, T, precision=precision)
     f64 = oracle.init_feq(rho, ux, uy, T)
     _, _, w, _ = oracle.model()
     g = host(lb.get_state())
@@ -50,49 +60,113 @@ def test_fp32_state_is_shifted_and_propagate_exact():
     assert np.array_equal(got[known], ref[known].astype(np.float32))
 
 
+# One step from the same FP32 state.  fp32s adds one FP32 rounding per
+# population (2^-24) to the oracle's step.  fp32c rounds its FP32 sums
+# relative to the deviation n from the rest Maxwellian (at most the size of f,
+# at the interface) with about 20 operations behind each output: a few 1e-7
+# of the largest population.  FP32 Hermite sums of f itself add ~20 ulp of the
+# largest term (coefficients up to He_4(3r) = 92).
+ONE_STEP_TOL = {"fp32s": 2e-7, "fp32c": 6e-7, "fp32s_f32sum": 1e-6}
+
+
 @pytest.mark.parametrize("layout", ["column", "soa"])
-@pytest.mark.parametrize("precision,tol", [("fp32s", 2e-7), ("fp32s_f32sum", 1e-6)])
+@pytest.mark.parametrize("precision", ["fp32s", "fp32c", "fp32s_f32sum"])
 @pytest.mark.parametrize("kernel", ["fused", "split"])
-def test_fp32_single_step_close_to_oracle(kernel, precision, tol, layout):
-    """One step from the same FP32-rounded state: the FP64-sum form adds one
-    FP32 rounding per population (6e-8) to the oracle's step; FP32 sums of 37
-    terms add up to ~20 more ulp of the largest term."""
+@pytest.mark.parametrize("regularize", [1, 0])
+def test_fp32_single_step_close_to_oracle(kernel, precision, layout, regularize):
     lx, ly = 64, 80
     rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=2)
-    f = oracle.run(oracle.init_feq(rho, ux, uy, T), oparams(), 5)
-    lb = LB(lx, ly, rho, ux, uy, T, precision=precision, kernel=kernel, layout=layout)
+    P = oparams(regularize=regularize)
+    f = oracle.run(oracle.init_feq(rho, ux, uy, T), P, 5)
+    lb = LB(lx, ly, rho, ux, uy, T, precision=precision, kernel=kernel, layout=layout,
+            regularize=regularize)
     _, _, w, _ = oracle.model()
     g0 = (f - w[:, None, None]).astype(np.float32)
     lb.set_state(torch.from_numpy(g0))
     lb.step(1)
-    ref = oracle.run(g0.astype(np.float64) + w[:, None, None], oparams(), 1)
+    ref = oracle.run(g0.astype(np.float64) + w[:, None, None], P, 1)
     got = host(lb.populations())
-    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("%s %s %s reg=%d one step: %.2e" % (precision, kernel, layout, regularize, err))
+    assert err <= ONE_STEP_TOL[precision]
 
 
-def test_fp32_vs_oracle_256_2000_steps():
-    lx, ly, steps = 256, 256, 2000
-    rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=workload.config_seed(3))
-    lb = LB(lx, ly, rho, ux, uy, T, precision="fp32s")
-    lb.step(steps)
-    m32 = [host(t) for t in lb.moments()]
-    ref = oracle.moments(oracle.run(oracle.init_feq(rho, ux, uy, T), oparams(), steps))
-    errs = field_errors(m32, ref)
-    print("fp32s vs oracle 256x256x2000:", errs)
+@pytest.mark.parametrize("rho_ref", [0.0, 1.3])
+@pytest.mark.parametrize("precision", ["fp32s", "fp32c"])
+def test_fp32_shift_density_single_step(precision, rho_ref):
+    """The shift density is a free parameter of the storage: one step from the
+    same stored values g = f - w rho_ref must match the oracle for any
+    rho_ref (rho_ref = 0: plain FP32 populations)."""
+    lx, ly = 64, 80
+    rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=2)
+    f = oracle.run(oracle.init_feq(rho, ux, uy, T), oparams(), 5)
+    lb = LB(lx, ly, rho, ux, uy, T, precision=precision, rho_ref=rho_ref)
+    _, _, w, _ = oracle.model()
+    g0 = (f - rho_ref * w[:, None, None]).astype(np.float32)
+    lb.set_state(torch.from_numpy(g0))
+    lb.step(1)
+    ref = oracle.run(g0.astype(np.float64) + rho_ref * w[:, None, None], oparams(), 1)
+    got = host(lb.populations())
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("%s rho_ref=%g one step: %.2e" % (precision, rho_ref, err))
+    assert err <= ONE_STEP_TOL[precision]
+
+
+@pytest.fixture(scope="module")
+def oracle_256_2000():
+    lx = ly = 256
+    f = workload.rt_fields(lx, ly, seed=workload.config_seed(3))[:4]
+    return f, oracle.moments(oracle.run(oracle.init_feq(*f), oparams(), 2000))
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp32s"])
+def test_fp32_vs_oracle_256_2000_steps(precision, oracle_256_2000):
+    fields, ref = oracle_256_2000
+    lb = LB(256, 256, *fields, precision=precision)
+    lb.step(2000)
+    errs = field_errors([host(t) for t in lb.moments()], ref)
+    print("%s vs oracle 256x256x2000:" % precision, errs)
+    assert worst(errs) <= 1e-5, errs
+
+
+def test_fp32_f32sum_ablation_stated_bound(oracle_256_2000):
+    """The FP32-sum ablation misses 1e-5; it is held to the bound stated for
+    it (per field, 256 x 256 x 2000 against the oracle)."""
+    fields, ref = oracle_256_2000
+    lb = LB(256, 256, *fields, precision="fp32s_f32sum")
+    lb.step(2000)
+    errs = field_errors([host(t) for t in lb.moments()], ref)
+    print("fp32s_f32sum vs oracle 256x256x2000:", errs)
+    assert max(errs["rho_max"], errs["T_max"]) <= 1e-4, errs
+    assert errs["u_max"] <= 3e-3, errs
+
+
+@pytest.mark.parametrize("rho_ref", [0.0, 1.3])
+@pytest.mark.parametrize("precision", ["fp32s", "fp32c"])
+def test_fp32_shift_density_vs_oracle_256_200_steps(precision, rho_ref):
+    lx = ly = 256
+    f = workload.rt_fields(lx, ly, seed=workload.config_seed(3))[:4]
+    ref = oracle.moments(oracle.run(oracle.init_feq(*f), oparams(), 200))
+    lb = LB(lx, ly, *f, precision=precision, rho_ref=rho_ref)
+    lb.step(200)
+    errs = field_errors([host(t) for t in lb.moments()], ref)
+    print("%s rho_ref=%g vs oracle 256x256x200:" % (precision, rho_ref), errs)
     assert worst(errs) <= 1e-5, errs
 
 
 def test_fp32_vs_fp64_gpu_4096_2000_steps():
     lx, ly, steps = 4096, 4096, 2000
-    rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=workload.config_seed(3))
-    lb64 = LB(lx, ly, rho, ux, uy, T, precision="fp64")
+    f = workload.rt_fields(lx, ly, seed=workload.config_seed(3))[:4]
+    lb64 = LB(lx, ly, *f, precision="fp64")
     lb64.step(steps)
     m64 = [host(t) for t in lb64.moments()]
     del lb64
     torch.cuda.empty_cache()
-    lb32 = LB(lx, ly, rho, ux, uy, T, precision="fp32s")
-    lb32.step(steps)
-    m32 = [host(t) for t in lb32.moments()]
-    errs = field_errors(m32, m64)
-    print("fp32s vs fp64 GPU 4096x4096x2000:", errs)
-    assert worst(errs) <= 1e-5, errs
+    for precision in ("fp32c", "fp32s"):
+        lb32 = LB(lx, ly, *f, precision=precision)
+        lb32.step(steps)
+        errs = field_errors([host(t) for t in lb32.moments()], m64)
+        del lb32
+        torch.cuda.empty_cache()
+        print("%s vs fp64 GPU 4096x4096x2000:" % precision, errs)
+        assert worst(errs) <= 1e-5, (precision, errs)

@@ -42,8 +42,12 @@ def oparams():
 
 @pytest.mark.parametrize("lx,ly,precision,mode,warm", [
     (1920, 2048, "fp64", "sinusoid", 50),
+    (1920, 2048, "fp32c", "sinusoid", 50),
     (4096, 4096, "fp32s", "sinusoid", 20),
+    (4096, 4096, "fp32c", "sinusoid", 20),
     (8192, 4096, "fp64", "multimode", 10),
+    (8192, 4096, "fp32s", "multimode", 10),
+    (8192, 4096, "fp32c", "multimode", 10),
 ])
 def test_one_step_at_sampled_sites(lx, ly, precision, mode, warm):
     seed = workload.config_seed({2048: 2, 4096: 3 if lx == 4096 else 5}[ly])
@@ -58,8 +62,12 @@ def test_one_step_at_sampled_sites(lx, ly, precision, mode, warm):
     ref = oracle.step_sites(state, oparams(), xs, ys)
     got = nxt[:, xs, ys].T
     # FP64: rounding of one step (1e-13 of the scale); FP32 storage: one
-    # rounding of each stored population (2^-24) plus the input's own rounding
-    tol = 1e-13 if precision == "fp64" else 3e-7
-    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    # rounding of each stored population (2^-24) plus the input's own
+    # rounding; the FP32 collision adds its FP32 sums of the deviation from
+    # the rest Maxwellian (a few 1e-7 of the largest population)
+    tol = {"fp64": 1e-13, "fp32s": 3e-7, "fp32c": 6e-7}[precision]
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("%s %dx%d one step at %d sampled sites: %.2e" % (precision, lx, ly, len(xs), err))
+    assert err <= tol
     del lb
     torch.cuda.empty_cache()
