@@ -29,8 +29,12 @@ Q = 37
 
 
 def bytes_per_site(precision: str = "fp64") -> int:
-    """Algorithmic HBM bytes of one site update: read and write 37 populations."""
-    return 2 * Q * (8 if precision == "fp64" else 4)
+    """Algorithmic HBM bytes of one site update: read and write 37 populations
+    (8 or 4 bytes each); the local-reference FP32 form ("fp32c") also reads
+    and writes its site's packed reference (4 bytes)."""
+    if precision == "fp64":
+        return 2 * Q * 8
+    return 2 * (Q + 1) * 4 if precision == "fp32c" else 2 * Q * 4
 
 
 def mlups(sites: int, seconds: float) -> float:
@@ -216,8 +220,9 @@ def time_split_kernels(lb, steps: int, torch) -> dict:
 # FP32 forms timed beside the FP64 headline: (key, precision, what it is)
 FP32_FORMS = (
     ("fp32_shifted", "fp32c",
-     "FP32 storage of f - w rho_ref and FP32 collision about the site's rest Maxwellian "
-     "(FP64 for the collision invariants and the equilibrium coefficients)"),
+     "FP32 storage of each population's deviation from its writer site's rest Maxwellian "
+     "(+ that site's FP16 density and temperature), FP32 collision (FP64 for the collision "
+     "invariants, the equilibrium coefficients and a conservation correction)"),
     ("fp32_storage_fp64_collide", "fp32s", "FP32 storage of f - w rho_ref, FP64 collision"),
     ("fp32_shifted_f32sum", "fp32s_f32sum",
      "ablation: FP32 storage, the FP64 collision's Hermite sums in FP32"),
@@ -246,7 +251,7 @@ def fp32_legs(lx: int, ly: int, fields, layout: str, fp64_mlups: float, torch) -
         lb32.step(FP32_ERROR_STEPS - FP32_WARMUP - FP32_TIMED)
         errs = field_errors(host_moments(lb32, torch), m64)
         v32 = mlups(sites * FP32_TIMED, t32)
-        gbs = bytes_per_site("fp32") * sites / (t32 / FP32_TIMED) / 1e9
+        gbs = bytes_per_site(prec) * sites / (t32 / FP32_TIMED) / 1e9
         out[key] = {
             "form": what, "precision": prec,
             "MLUPS": round(v32, 2), "ms_per_step": round(t32 / FP32_TIMED * 1e3, 5),
@@ -291,7 +296,7 @@ def production_leg(torch, steps: int = 200, warmup: int = 10, n_adj: int = 100,
         lb.step(warmup)
         t = time_steps(lb, steps, torch)
         v = mlups(sites * steps, t)
-        gbs = bytes_per_site("fp64" if prec == "fp64" else "fp32") * sites / (t / steps) / 1e9
+        gbs = bytes_per_site(prec) * sites / (t / steps) / 1e9
         rec[prec] = {"MLUPS": round(v, 1), "ms_per_step": round(t / steps * 1e3, 4),
                      "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                      "workspace_bytes": ws}
@@ -407,11 +412,15 @@ def _parity_workload(P, torch) -> dict:
     lb = LB(lx, ly, *f)
     lb.step(n)
     m = host_moments(lb, torch)
+    f0 = oracle.init_feq(*f)
     t0 = time.perf_counter()
-    ref = oracle.moments(oracle.run(oracle.init_feq(*f), P, n))
+    ref = oracle.moments(oracle.run(f0, P, n))
     t_or = time.perf_counter() - t0
+    ext = oracle.run_moments_extended(f0, P, n)
     rec = {"workload": "parity 256x128", "lattice": [lx, ly], "steps": n, "precision": "fp64",
+           "error_vs_extended_oracle": field_errors(m, ext),
            "error_vs_oracle": field_errors(m, ref),
+           "oracle_fp64_vs_extended": field_errors(ref, ext),
            "oracle": {"MLUPS": round(mlups(lx * ly * n, t_or), 2), "seconds": round(t_or, 3),
                       "threads": oracle.get_threads()}}
     log("workloads: %s" % rec)
@@ -553,18 +562,18 @@ def _production_workload(args, torch) -> dict:
     seed = workload.config_seed(5)
     rho, ux, uy, T, info = workload.rt_fields(lx, ly, seed=seed, mode="multimode")
     rec = {"workload": "production 8192x4096", "lattice": [lx, ly], "steps": n}
-    for prec in ("fp32s", "fp64"):
+    for prec in ("fp32c", "fp32s", "fp64"):
         base = device_bytes_in_use(torch)
         lb = LB(lx, ly, rho, ux, uy, T, precision=prec)
         foot = device_bytes_in_use(torch) - base
         t = time_steps(lb, n - (n_adj if prec == "fp64" else 0), torch)
         steps_done = n - (n_adj if prec == "fp64" else 0)
         v = mlups(sites * steps_done, t)
-        bps = bytes_per_site("fp64" if prec == "fp64" else "fp32")
+        bps = bytes_per_site(prec)
         rec[prec] = {"MLUPS": round(v, 1), "GB/s": round(bps * v * 1e6 / 1e9, 1),
                      "hbm_frac": round(bps * v * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
                      "workspace_GB": round(foot / 1e9, 3), "steps_timed": steps_done}
-        if prec == "fp32s":
+        if prec != "fp64":
             del lb
             torch.cuda.empty_cache()
     # adjoint of the last n_adj steps: d KE(final) / d (state at step n - n_adj)
@@ -716,7 +725,7 @@ def run_ablations(args, torch) -> list:
     m64 = host_moments(lb, torch)
     del lb
     shift = {}
-    for prec in ("fp32c", "fp32s", "fp32s_f32sum"):
+    for prec in ("fp32s", "fp32s_f32sum"):
         for rho_ref in (0.0, 1.0):
             lb = LB(al, al, *fa, precision=prec, rho_ref=rho_ref)
             lb.step(n)

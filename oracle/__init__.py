@@ -109,6 +109,8 @@ def lib():
         L.oracle_step_sites.argtypes = [i, i, pp, dp, i, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32), dp]
         L.oracle_step_sites.restype = None
+        L.oracle_run_moments_ld.argtypes = [i, i, pp, dp, i, dp, dp, dp, dp, dp]
+        L.oracle_run_moments_ld.restype = None
         L.oracle_run_complex.argtypes = [i, i, pp, dp, i]
         L.oracle_run_complex.restype = None
         L.oracle_init_feq_complex.argtypes = [i, i, dp, dp, dp, dp, dp]
@@ -235,6 +237,21 @@ def moments(f):
     rho, ux, uy, T = (np.zeros((lx, ly)) for _ in range(4))
     lib().oracle_moments(lx, ly, _p(f), _p(rho), _p(ux), _p(uy), _p(T))
     return rho, ux, uy, T
+
+
+def run_moments_extended(f, params: Params, nsteps: int, with_populations: bool = False):
+    """nsteps full steps from f in long double (x87, 64-bit significand) and
+    the Eq. (2) moments of the result, rounded to FP64: (rho, ux, uy, T), plus
+    the populations when asked.  The reference against which the rounding
+    of FP64 runs (this oracle's and the GPU's) is measured."""
+    f = _f64(f)
+    _, lx, ly = f.shape
+    rho, ux, uy, T = (np.zeros((lx, ly)) for _ in range(4))
+    out = np.zeros_like(f) if with_populations else None
+    P = params.c()
+    lib().oracle_run_moments_ld(lx, ly, ctypes.byref(P), _p(f), int(nsteps), _p(rho), _p(ux),
+                                _p(uy), _p(T), _p(out) if out is not None else None)
+    return (rho, ux, uy, T, out) if with_populations else (rho, ux, uy, T)
 
 
 def kinetic_energy(f) -> float:

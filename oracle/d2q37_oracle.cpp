@@ -25,7 +25,10 @@
 // the readings are stated next to the code that takes them.
 //
 // Every routine is templated on the scalar type so that the same source runs
-// in double and in std::complex<double> (complex-step differentiation).
+// in double, in std::complex<double> (complex-step differentiation) and in
+// long double (x87 extended precision, 64-bit significand: the same model
+// constants with 11 more bits in every operation, which measures how much of
+// a difference between two FP64 implementations is FP64 rounding).
 // Built with -O2 -ffp-contract=off, no fast-math.
 
 #include <quadmath.h>
@@ -68,6 +71,8 @@ struct Model {
   double w[Q];
   double r;
   double H[Q][5][5];  // He_p(r cx_l) He_q(r cy_l), filled for p + q <= 4
+  // the same constants rounded from the binary128 solve to long double
+  long double wx[Q], rx, Hx[Q][5][5];
   bool ok;
 };
 
@@ -145,13 +150,13 @@ bool solve_spd(quad N[8][8], quad b[8], quad x[8]) {
 }
 
 // Probabilists' Hermite polynomials He_0..He_4.
-double hermite_d(int n, double x) {
+quad hermite_q(int n, quad x) {
   switch (n) {
-    case 0: return 1.0;
+    case 0: return quad(1);
     case 1: return x;
-    case 2: return x * x - 1.0;
-    case 3: return x * x * x - 3.0 * x;
-    default: return x * x * x * x - 6.0 * x * x + 3.0;
+    case 2: return x * x - 1;
+    case 3: return x * x * x - 3 * x;
+    default: return x * x * x * x - 6 * x * x + 3;
   }
 }
 
@@ -224,11 +229,24 @@ Model build_model() {
   if (!solve_spd(N, b, W)) M.ok = false;
   M.r = (double)r;
   for (int l = 0; l < Q; ++l) M.w[l] = (double)W[M.fam[l]];
+  M.rx = (long double)r;
+  for (int l = 0; l < Q; ++l) M.wx[l] = (long double)W[M.fam[l]];
   for (int l = 0; l < Q; ++l)
     for (int p = 0; p <= 4; ++p)
       for (int q = 0; q <= 4; ++q)
-        M.H[l][p][q] = (p + q <= 4) ? hermite_d(p, M.r * M.cx[l]) *
-                                          hermite_d(q, M.r * M.cy[l])
+        M.Hx[l][p][q] = (p + q <= 4) ? (long double)(hermite_q(p, r * M.cx[l]) *
+                                                      hermite_q(q, r * M.cy[l]))
+                                     : 0.0L;
+  // The Hermite table is rounded once from its binary128 value: evaluated in
+  // FP64 from the rounded r, He_4(2r) = 16r^4 - 24r^2 + 3 would lose about
+  // eight bits to cancellation, a perturbation of the model that the
+  // Rayleigh-Taylor flow carries into the velocity field (~1e-12 of max|u|
+  // after 50 steps).
+  for (int l = 0; l < Q; ++l)
+    for (int p = 0; p <= 4; ++p)
+      for (int q = 0; q <= 4; ++q)
+        M.H[l][p][q] = (p + q <= 4) ? (double)(hermite_q(p, r * M.cx[l]) *
+                                               hermite_q(q, r * M.cy[l]))
                                     : 0.0;
   return M;
 }
@@ -237,6 +255,24 @@ const Model& model() {
   static const Model M = build_model();
   return M;
 }
+
+// The model's constants in the working precision of S: the FP64 ones for
+// double and complex<double>; for long double the ones rounded from the
+// binary128 solve to long double, so that a long double run evaluates the
+// model of the unrounded quadrature (to ~1e-19) rather than the FP64-rounded
+// one.
+template <class S>
+struct Consts {
+  static double w(int l) { return model().w[l]; }
+  static double r() { return model().r; }
+  static double H(int l, int p, int q) { return model().H[l][p][q]; }
+};
+template <>
+struct Consts<long double> {
+  static long double w(int l) { return model().wx[l]; }
+  static long double r() { return model().rx; }
+  static long double H(int l, int p, int q) { return model().Hx[l][p][q]; }
+};
 
 double factorial(int n) {
   double v = 1;
@@ -273,12 +309,12 @@ double factorial(int n) {
 template <class S>
 void equilibrium(S rho, S ux, S uy, S T, S* feq) {
   const Model& M = model();
-  const double r = M.r;
+  const auto r = Consts<S>::r();
   const S th = T - 1.0;
   const S U2 = ux * ux + uy * uy;
   for (int l = 0; l < Q; ++l) {
-    const double xx = r * M.cx[l], xy = r * M.cy[l];
-    const double x2 = xx * xx + xy * xy;
+    const auto xx = r * M.cx[l], xy = r * M.cy[l];
+    const auto x2 = xx * xx + xy * xy;
     const S xu = xx * ux + xy * uy;
     const S t1 = xu;
     const S t2 = (xu * xu - U2 + th * (x2 - 2.0)) / 2.0;
@@ -287,7 +323,7 @@ void equilibrium(S rho, S ux, S uy, S T, S* feq) {
                   6.0 * th * (xu * xu * (x2 - 6.0) + U2 * (4.0 - x2)) +
                   3.0 * th * th * (x2 * x2 - 8.0 * x2 + 8.0)) /
                  24.0;
-    feq[l] = M.w[l] * rho * (1.0 + t1 + t2 + t3 + t4);
+    feq[l] = Consts<S>::w(l) * rho * (1.0 + t1 + t2 + t3 + t4);
   }
 }
 
@@ -295,10 +331,10 @@ void equilibrium(S rho, S ux, S uy, S T, S* feq) {
 template <class S>
 void macroscopic(const S* f, S& rho, S& ux, S& uy, S& T) {
   const Model& M = model();
-  const double r = M.r;
+  const auto r = Consts<S>::r();
   S m0(0.0), jx(0.0), jy(0.0), e(0.0);
   for (int l = 0; l < Q; ++l) {
-    const double cx = r * M.cx[l], cy = r * M.cy[l];
+    const auto cx = r * M.cx[l], cy = r * M.cy[l];
     m0 += f[l];
     jx += cx * f[l];
     jy += cy * f[l];
@@ -426,7 +462,12 @@ void collide_site(const Params& P, const S* ft, S* out) {
   const S Ts = T + tau * (1.0 - tau) * (P.gx * P.gx + P.gy * P.gy) / 2.0;
   S feq[Q], h[Q];
   equilibrium<S>(rho, uxs, uys, Ts, feq);
-  for (int l = 0; l < Q; ++l) h[l] = (1.0 - 1.0 / tau) * ft[l] + feq[l] / tau;
+  // the two BGK weights, 1/tau and 1 - 1/tau, are formed once in the working
+  // precision; their sum is then exactly one (1 - omega is exact for
+  // 1/2 <= omega <= 2), so the relaxation itself adds no bias to the mass
+  const S omega = S(1.0) / S(tau);
+  const S keep = S(1.0) - omega;
+  for (int l = 0; l < Q; ++l) h[l] = keep * ft[l] + omega * feq[l];
   if (!P.regularize) {
     for (int l = 0; l < Q; ++l) out[l] = h[l];
     return;
@@ -435,15 +476,15 @@ void collide_site(const Params& P, const S* ft, S* out) {
   for (int p = 0; p <= 4; ++p)
     for (int q = 0; p + q <= 4; ++q) {
       S a(0.0);
-      for (int m = 0; m < Q; ++m) a += h[m] * M.H[m][p][q];
+      for (int m = 0; m < Q; ++m) a += h[m] * Consts<S>::H(m, p, q);
       A[p][q] = a;
     }
   for (int l = 0; l < Q; ++l) {
     S s(0.0);
     for (int p = 0; p <= 4; ++p)
       for (int q = 0; p + q <= 4; ++q)
-        s += A[p][q] * M.H[l][p][q] / (factorial(p) * factorial(q));
-    out[l] = M.w[l] * s;
+        s += A[p][q] * Consts<S>::H(l, p, q) / (factorial(p) * factorial(q));
+    out[l] = Consts<S>::w(l) * s;
   }
 }
 
@@ -623,6 +664,33 @@ void oracle_ke_after_steps_complex(int lx, int ly, const Params* P,
   const cplx k = kinetic_energy<cplx>(lx, ly, f.data());
   ke[0] = k.real();
   ke[1] = k.imag();
+}
+
+// Extended-precision run: f (FP64 [37][lx][ly]) advanced by nsteps full steps
+// in long double; the moments of Eq. (2) of the result, also in long double,
+// rounded to FP64 into rho, ux, uy, T ([lx][ly]); the populations into
+// f_out when it is not NULL.
+void oracle_run_moments_ld(int lx, int ly, const Params* P, const double* f, int nsteps,
+                           double* rho, double* ux, double* uy, double* T, double* f_out) {
+  using ld = long double;
+  const size_t S = (size_t)lx * ly;
+  std::vector<ld> g((size_t)Q * S), tmp((size_t)Q * S);
+  for (size_t i = 0; i < (size_t)Q * S; ++i) g[i] = f[i];
+  for (int n = 0; n < nsteps; ++n) step<ld>(lx, ly, *P, g.data(), tmp.data());
+  for (int x = 0; x < lx; ++x)
+    for (int y = 0; y < ly; ++y) {
+      ld in[Q];
+      for (int l = 0; l < Q; ++l) in[l] = g[idx(l, x, y, lx, ly)];
+      ld r, u, v, t;
+      macroscopic<ld>(in, r, u, v, t);
+      const long s = (long)x * ly + y;
+      rho[s] = double(r);
+      ux[s] = double(u);
+      uy[s] = double(v);
+      T[s] = double(t);
+    }
+  if (f_out)
+    for (size_t i = 0; i < (size_t)Q * S; ++i) f_out[i] = double(g[i]);
 }
 
 // Complex-step forms for linearisations: f_c is complex [37][lx][ly]

@@ -40,6 +40,8 @@ struct Geom {
   int nx, ny;      // padded sizes (nx = lx + 2*HX)
   int hy;          // physical row 0 is padded row hy (hy >= 3)
   int walls;       // 1: thermal walls in y, 0: periodic y
+  int np;          // planes per padded site: Q, or Q + 1 in the local-reference
+                   // form (its packed reference)
   long long ps;    // element stride between populations
   long long cs;    // element stride between padded columns
 };
@@ -333,35 +335,19 @@ __device__ __forceinline__ Tape4 collide_site(A (&f)[Q], const Phys& P) {
 }
 
 // ---------------------------------------------------------------------------
-// FP32 collision relative to a local reference (the FP32-arithmetic form).
+// FP32 storage relative to the local rest Maxwellian, and the FP32 collision.
 //
-// FP32 rounding is relative to the size of the numbers summed.  The
-// populations of a site lie close to its rest Maxwellian
-//   R_l = w_l rho [1 + th_R (|c_l|^2 - 2)/2 + th_R^2 (|c_l|^4 - 8|c_l|^2 + 8)/8]
-// (f^eq at u = 0 and temperature 1 + th_R, Eq. (2) moments exact), so the
-// non-conserved part of the collision is computed in FP32 on n_l = f_l - R_l,
-// small wherever the flow is slow and near equilibrium, while the collision
-// invariants are summed in FP64:
-//   1. FP64 sums of the stored values: mass rho, momentum j, energy
-//      E = sum |c|^2 f; th_R = E / (2 rho) - 1, so n carries no mass and no
-//      energy and its momentum is j;
-//   2. R_l - w_l rho_ref per weight family (|e_l|^2 fixes w_l and |c_l|^2),
-//      in FP64, kept as an unevaluated FP32 pair hi + lo;
-//   3. n_l = (g_l - hi) - lo in FP32 (the first difference is exact or off
-//      by half an ulp of n);
-//   4. the Hermite coefficients of n in FP32 (the FP32-accumulated moments),
-//      with a_00 = 0, a_10 = j_x, a_01 = j_y and a_20 + a_02 = 0 taken from
-//      step 1 instead;
-//   5. the forced equilibrium coefficients in FP64 at rho, u = j / rho,
-//      th = th_R - |u|^2 / 2 (Hermite orders up to four, where cancellation
-//      against the reference needs the digits); d_pq = a^eq_pq - a^R_pq
-//      rounded to FP32, with a^R_00 = rho, a^R_20 = a^R_02 = rho th_R,
-//      a^R_40 = a^R_04 = 3 rho th_R^2, a^R_22 = rho th_R^2, all others 0;
-//   6. the relaxed deviation b_pq = (1 - 1/tau) a^n_pq + d_pq / tau
-//      (regularized) reconstructed in FP32 as r_l; plain BGK relaxes n_l
-//      itself and adds the reconstruction of d / tau;
-//   7. g'_l = hi + (lo + r_l): one FP32 rounding of the stored value.
-// g holds f_l - w_l rho_ref in FP32 on entry and on return.
+// A population is stored as its deviation from the rest Maxwellian of the
+// site that last collided it,
+//   g_l = f_l - M_l(rho_s, th_s),
+//   M_l(rho, th) = w_l rho [1 + th (|c_l|^2 - 2)/2 + th^2 (|c_l|^4 - 8|c_l|^2 + 8)/8]
+// (f^eq at u = 0 and temperature 1 + th, exact Eq. (2) moments), in FP32,
+// and that site's (rho_s, th_s) as two FP16 numbers packed into one 32-bit
+// word: a 38th plane beside the 37 populations.  The deviation carries only
+// the flow and the non-equilibrium part of f (a few per cent of f in a slow
+// flow), so its FP32 rounding is that much smaller than a rounding of f or of
+// f - w_l rho_0.  The FP16 reference needs no accuracy of its own: writer and
+// reader evaluate M from the same stored pair, in FP64.
 // ---------------------------------------------------------------------------
 constexpr int kFamilies = 8;
 // weight family of hop l, numbered by |e_l|^2 = 0, 1, 2, 4, 5, 8, 9, 10
@@ -378,10 +364,73 @@ __host__ __device__ constexpr int family_of(int l) {
 constexpr int kFamilyE2[kFamilies] = {0, 1, 2, 4, 5, 8, 9, 10};
 // a hop of each family (for its weight)
 constexpr int kFamilyLabel[kFamilies] = {18, 17, 10, 16, 9, 3, 15, 8};
+// hops (0,0), (1,0), (-1,0), (0,1), (0,-1): the populations that absorb the
+// conservation correction of the FP32 reconstruction
+constexpr int kRest = 18, kEast = 11, kWest = 25, kNorth = 19, kSouth = 17;
+// planes of a padded buffer in the local-reference form: 37 deviations + the
+// packed reference
+constexpr int kLocalPlanes = Q + 1;
 
+__device__ __forceinline__ double rest_maxwellian(int l, double rho, double th) {
+  const double x2 = c2(l);
+  const double c1 = 0.5 * (x2 - 2.0), c2q = 0.125 * (x2 * x2 - 8.0 * x2 + 8.0);
+  return (W[l] * rho) * fma(th, fma(c2q, th, c1), 1.0);
+}
+
+// (rho_s, th_s) <-> one 32-bit word of two FP16 numbers (rho_s low, th_s high)
+__device__ __forceinline__ unsigned pack_ref(double rho, double th) {
+  const unsigned short a = __builtin_bit_cast(unsigned short, (_Float16)float(rho));
+  const unsigned short b = __builtin_bit_cast(unsigned short, (_Float16)float(th));
+  return unsigned(a) | (unsigned(b) << 16);
+}
+__device__ __forceinline__ void unpack_ref(unsigned v, double& rho, double& th) {
+  rho = double(float(__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu))));
+  th = double(float(__builtin_bit_cast(_Float16, (unsigned short)(v >> 16))));
+}
+
+// The reference a site takes from its FP64 populations: its density and
+// th_s = sum |c|^2 f / (2 rho) - 1, rounded to FP16; the deviations from it.
+__device__ __forceinline__ unsigned encode_site(const double (&f)[Q], float (&g)[Q]) {
+  double rho = 0.0, e2 = 0.0;
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    rho += f[l];
+    e2 += c2(l) * f[l];
+  }
+  const unsigned ref = pack_ref(rho, 0.5 * e2 / rho - 1.0);
+  double rs, ts;
+  unpack_ref(ref, rs, ts);
+#pragma unroll
+  for (int l = 0; l < Q; ++l) g[l] = float(f[l] - rest_maxwellian(l, rs, ts));
+  return ref;
+}
+
+// Collision of one site from its FP64 populations f (rebuilt from the stored
+// deviations and their writers' references); returns the site's new packed
+// reference and writes the post-collision deviations g from it:
+//   1. collision invariants in FP64: rho, momentum j, energy E = sum |c|^2 f;
+//      new reference (rho, E / (2 rho) - 1) rounded to FP16;
+//   2. n_l = f_l - M_l(rho_s, th_s) in FP64, rounded to FP32;
+//   3. Hermite coefficients of n in FP32 (the FP32-accumulated moments), the
+//      invariant ones (a_00, a_10, a_01, a_20 + a_02) from step 1 instead;
+//   4. the forced equilibrium coefficients in FP64 (Hermite orders up to
+//      four) minus those of the reference, and the relaxed deviation
+//      b_pq = (1 - 1/tau) a^n_pq + (a^eq_pq - a^M_pq) / tau in FP64, rounded
+//      once to FP32 (a^M: a_00 = rho_s, a_20 = a_02 = rho_s th_s,
+//      a_40 = a_04 = 3 rho_s th_s^2, a_22 = rho_s th_s^2, the others 0);
+//   5. g_l = w_l sum_pq b_pq H_pq(c_l) / (p! q!) in FP32, the orders 0 and 1
+//      (mass and momentum) reconstructed on their own and added last;
+//   6. conservation: the invariants of the FP32 values g are summed in FP64
+//      and their shortfall against b_00, b_10, b_01, b_20 + b_02 (exact) is
+//      put into the five populations (0,0), (+-1,0), (0,+-1) (in FP32
+//      rounding errors are systematic over a slowly varying flow, and a
+//      shortfall in an invariant would accumulate from step to step).
+// Plain BGK relaxes n itself: g = (1 - 1/tau) n + reconstruction of
+// (a^eq - a^M) / tau, with the same correction.
 template <bool kRegularize>
-__device__ __forceinline__ void collide_site_ref(float (&g)[Q], const Phys& P) {
-  // 1. collision invariants in FP64: per-family, per-e_x and per-e_y sums
+__device__ __forceinline__ unsigned collide_site_local(const double (&f)[Q], float (&g)[Q],
+                                                       const Phys& P) {
+  // 1. invariants: per-family, per-e_x and per-e_y sums
   double sf[kFamilies], sx[7], sy[7];
 #pragma unroll
   for (int k = 0; k < kFamilies; ++k) sf[k] = 0.0;
@@ -389,15 +438,14 @@ __device__ __forceinline__ void collide_site_ref(float (&g)[Q], const Phys& P) {
   for (int k = 0; k < 7; ++k) sx[k] = sy[k] = 0.0;
 #pragma unroll
   for (int l = 0; l < Q; ++l) {
-    const double v = double(g[l]);
-    sf[family_of(l)] += v;
-    if (EX[l] != 0) sx[EX[l] + 3] += v;
-    if (EY[l] != 0) sy[EY[l] + 3] += v;
+    sf[family_of(l)] += f[l];
+    if (EX[l] != 0) sx[EX[l] + 3] += f[l];
+    if (EY[l] != 0) sy[EY[l] + 3] += f[l];
   }
-  double s0 = 0.0, s2 = 0.0, jx = 0.0, jy = 0.0;
+  double rho = 0.0, s2 = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
   for (int k = 0; k < kFamilies; ++k) {
-    s0 += sf[k];
+    rho += sf[k];
     s2 += double(kFamilyE2[k]) * sf[k];
   }
 #pragma unroll
@@ -405,96 +453,118 @@ __device__ __forceinline__ void collide_site_ref(float (&g)[Q], const Phys& P) {
     jx += double(e) * (sx[3 + e] - sx[3 - e]);
     jy += double(e) * (sy[3 + e] - sy[3 - e]);
   }
-  // the shift w rho_ref adds rho_ref to the mass and 2 rho_ref to the energy
-  const double rho = P.rho_ref + s0;
-  const double inv_rho = 1.0 / rho;
-  const double th_r = 0.5 * (R * R * s2 + 2.0 * P.rho_ref) * inv_rho - 1.0;
   jx *= R;
   jy *= R;
-  // 2. reference per family: w (R/w - rho_ref) as hi + lo
-  float hi[kFamilies], lo[kFamilies];
+  const double inv_rho = 1.0 / rho;
+  const double e2 = R * R * s2;  // sum |c|^2 f
+  const unsigned ref = pack_ref(rho, 0.5 * e2 * inv_rho - 1.0);
+  double rs, ts;
+  unpack_ref(ref, rs, ts);
+  // 2. deviation from the new reference
+  double m[kFamilies];
 #pragma unroll
-  for (int k = 0; k < kFamilies; ++k) {
-    const double x2 = R * R * double(kFamilyE2[k]);
-    const double c1 = 0.5 * (x2 - 2.0), c2 = 0.125 * (x2 * x2 - 8.0 * x2 + 8.0);
-    const double v = W[kFamilyLabel[k]] * (rho * (1.0 + th_r * (c1 + c2 * th_r)) - P.rho_ref);
-    hi[k] = float(v);
-    lo[k] = float(v - double(hi[k]));
-  }
-  // 3. deviation from the reference
+  for (int k = 0; k < kFamilies; ++k) m[k] = rest_maxwellian(kFamilyLabel[k], rs, ts);
   float n[Q];
 #pragma unroll
-  for (int l = 0; l < Q; ++l) n[l] = (g[l] - hi[family_of(l)]) - lo[family_of(l)];
-  // 4. FP32 Hermite coefficients of n
+  for (int l = 0; l < Q; ++l) n[l] = float(f[l] - m[family_of(l)]);
+  // 3. FP32 Hermite coefficients of n
   float an[5][5];
   project<float>(n, an);
-  // 5. forced equilibrium minus the reference and the relaxed deviation, in
-  // FP64, rounded once to FP32.  The invariants come from step 1: n has no
-  // mass, momentum j and a_20 + a_02 = 0.
+  // 4. equilibrium minus reference, relaxation (FP64, one rounding)
   const double ux = jx * inv_rho, uy = jy * inv_rho;
-  const double th = th_r - 0.5 * (ux * ux + uy * uy);
+  const double th = 0.5 * (e2 * inv_rho - (ux * ux + uy * uy)) - 1.0;
   double aeq[5][5];
   equilibrium_coeffs(rho, ux + P.tau_gx, uy + P.tau_gy, th + P.dtheta, aeq);
-  const double th2 = th_r * th_r;
-  const double aR20 = rho * th_r, aR40 = 3.0 * rho * th2, aR22 = rho * th2;
-  const double om = P.omega, keep = 1.0 - P.omega;
+  const double aM20 = rs * ts, aM40 = 3.0 * rs * ts * ts, aM22 = rs * ts * ts;
+  // a_20 + a_02 is sum (|c|^2 - 2) f: E - 2 rho for f, 2 aM20 for the reference
+  const double sum2 = (e2 - 2.0 * rho) - 2.0 * aM20;
   const double half_diff = 0.5 * (double(an[2][0]) - double(an[0][2]));
+  const double om = P.omega, keep = 1.0 - P.omega;
   float b[5][5];
+  double b00 = 0.0, b10 = 0.0, b01 = 0.0, b2 = 0.0;
 #pragma unroll
   for (int p = 0; p < 5; ++p)
 #pragma unroll
     for (int q = 0; q + p < 5; ++q) {
-      double ar = 0.0, a = double(an[p][q]);
-      if ((p == 2 && q == 0) || (p == 0 && q == 2)) ar = aR20;
-      if ((p == 4 && q == 0) || (p == 0 && q == 4)) ar = aR40;
-      if (p == 2 && q == 2) ar = aR22;
+      double am = 0.0, a = double(an[p][q]);
+      if (p == 0 && q == 0) {
+        am = rs;
+        a = rho - rs;
+      }
+      if ((p == 2 && q == 0) || (p == 0 && q == 2)) am = aM20;
+      if ((p == 4 && q == 0) || (p == 0 && q == 4)) am = aM40;
+      if (p == 2 && q == 2) am = aM22;
       if (p == 1 && q == 0) a = jx;
       if (p == 0 && q == 1) a = jy;
-      if (p == 2 && q == 0) a = half_diff;
-      if (p == 0 && q == 2) a = -half_diff;
-      b[p][q] = float(kRegularize ? keep * a + om * (aeq[p][q] - ar) : om * (aeq[p][q] - ar));
+      if (p == 2 && q == 0) a = 0.5 * sum2 + half_diff;
+      if (p == 0 && q == 2) a = 0.5 * sum2 - half_diff;
+      const double dm = (p == 0 && q == 0) ? rho - rs : aeq[p][q] - am;
+      const double bv = kRegularize ? keep * a + om * dm : om * dm;
+      b[p][q] = float(bv);
+      if (p == 0 && q == 0) b00 = bv;
+      if (p == 1 && q == 0) b10 = bv;
+      if (p == 0 && q == 1) b01 = bv;
+      if (p + q == 2 && p != 1) b2 += bv;
     }
-  b[0][0] = 0.0f;  // a^eq_00 = rho = a^R_00: collision conserves mass
-  // 6. reconstruct the deviation in FP32; the first-order (momentum) terms
-  // on their own, not rounded inside the column sums of the larger
-  // higher-order terms
+  if (!kRegularize) {
+    // BGK: the invariants of (1 - 1/tau) n come on top of those of d / tau
+    b00 += keep * (rho - rs);
+    b10 += keep * jx;
+    b01 += keep * jy;
+    b2 += keep * sum2;
+  }
+  // 5. FP32 reconstruction of the deviation
   float r[Q];
   reconstruct<float, 2>(b, r);
 #pragma unroll
   for (int l = 0; l < Q; ++l) {
-    float r1 = 0.0f;
+    float r1 = float(W[l]) * b[0][0];
     if (EX[l] != 0) r1 += float(W[l] * R * EX[l]) * b[1][0];
     if (EY[l] != 0) r1 += float(W[l] * R * EY[l]) * b[0][1];
-    r[l] = kRegularize ? r1 + r[l] : float(keep) * n[l] + (r1 + r[l]);
+    g[l] = kRegularize ? r1 + r[l] : float(keep) * n[l] + (r1 + r[l]);
   }
-  // 7. back to stored values
+  // 6. conservation correction
+  double cf[kFamilies], cx[7], cy[7];
 #pragma unroll
-  for (int l = 0; l < Q; ++l) g[l] = hi[family_of(l)] + (lo[family_of(l)] + r[l]);
+  for (int k = 0; k < kFamilies; ++k) cf[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) cx[k] = cy[k] = 0.0;
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    const double v = double(g[l]);
+    cf[family_of(l)] += v;
+    if (EX[l] != 0) cx[EX[l] + 3] += v;
+    if (EY[l] != 0) cy[EY[l] + 3] += v;
+  }
+  double m0 = 0.0, m2 = 0.0, mx = 0.0, my = 0.0;
+#pragma unroll
+  for (int k = 0; k < kFamilies; ++k) {
+    m0 += cf[k];
+    m2 += (R * R * double(kFamilyE2[k]) - 2.0) * cf[k];
+  }
+#pragma unroll
+  for (int e = 1; e <= 3; ++e) {
+    mx += double(e) * (cx[3 + e] - cx[3 - e]);
+    my += double(e) * (cy[3 + e] - cy[3 - e]);
+  }
+  const double dm0 = b00 - m0, dx = b10 - R * mx, dy = b01 - R * my, d2 = b2 - m2;
+  // corrections z (rest), a, b (east, west), c, d (north, south) with
+  //   z + a + b + c + d = dm0, R (a - b) = dx, R (c - d) = dy,
+  //   -2 z + (R^2 - 2)(a + b + c + d) = d2, a + b = c + d
+  const double sq = (d2 + 2.0 * dm0) / (R * R);
+  g[kRest] = float(double(g[kRest]) + (dm0 - sq));
+  g[kEast] = float(double(g[kEast]) + 0.5 * (0.5 * sq + dx / R));
+  g[kWest] = float(double(g[kWest]) + 0.5 * (0.5 * sq - dx / R));
+  g[kNorth] = float(double(g[kNorth]) + 0.5 * (0.5 * sq + dy / R));
+  g[kSouth] = float(double(g[kSouth]) + 0.5 * (0.5 * sq - dy / R));
+  return ref;
 }
 
-// Collision dispatch on the accumulation type: double or float run
-// collide_site in that type; F32Ref (populations in float registers) runs
-// collide_site_ref.  The tape is produced by the FP64 form only.
-struct F32Ref {};
-template <class A>
-struct reg_of {
-  using type = A;
-};
-template <>
-struct reg_of<F32Ref> {
-  using type = float;
-};
-template <class A>
-using reg_t = typename reg_of<A>::type;
-
+// Collision dispatch on the accumulation type of the FP64 and shifted FP32
+// forms (the local-reference form has kernels of its own).
 template <class A, bool kRegularize>
-__device__ __forceinline__ Tape4 collide(reg_t<A> (&f)[Q], const Phys& P) {
-  if constexpr (std::is_same<A, F32Ref>::value) {
-    collide_site_ref<kRegularize>(f, P);
-    return Tape4{0.0, 0.0, 0.0, 0.0};
-  } else {
-    return collide_site<A, kRegularize>(f, P);
-  }
+__device__ __forceinline__ Tape4 collide(A (&f)[Q], const Phys& P) {
+  return collide_site<A, kRegularize>(f, P);
 }
 
 }  // namespace d2q37

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "d2q37_launch.h"
 
@@ -85,6 +86,36 @@ __device__ __forceinline__ void store_site(S* __restrict__ dst, const Geom& g, l
   for (int l = 0; l < Q; ++l) __builtin_nontemporal_store(S(f[l]), &dst[l * g.ps + site]);
 }
 
+// Accumulation-type tag of the local-reference FP32 form (populations stored
+// as FP32 deviations from the rest Maxwellian of their writer site, plus
+// that site's packed reference in plane Q; collide_site_local).
+struct LocalRef {};
+template <class A>
+constexpr bool is_local = std::is_same<A, LocalRef>::value;
+
+// The packed reference word of padded site `site` (plane Q).
+__device__ __forceinline__ unsigned ref_at(const float* __restrict__ buf, const Geom& g,
+                                           long long site) {
+  return reinterpret_cast<const unsigned*>(buf)[Q * g.ps + site];
+}
+
+// FP64 populations of one padded site in the local-reference form: all 37
+// deviations are relative to the site's own reference.
+__device__ __forceinline__ void load_local(const float* __restrict__ src, const Geom& g,
+                                           long long site, double (&f)[Q]) {
+  double rho, th;
+  unpack_ref(ref_at(src, g, site), rho, th);
+#pragma unroll
+  for (int l = 0; l < Q; ++l) f[l] = rest_maxwellian(l, rho, th) + double(src[l * g.ps + site]);
+}
+
+__device__ __forceinline__ void store_local(float* __restrict__ dst, const Geom& g, long long site,
+                                            const float (&v)[Q], unsigned ref) {
+#pragma unroll
+  for (int l = 0; l < Q; ++l) __builtin_nontemporal_store(v[l], &dst[l * g.ps + site]);
+  __builtin_nontemporal_store(ref, &reinterpret_cast<unsigned*>(dst)[Q * g.ps + site]);
+}
+
 // Adjoint arrays are compact (no halos) in the lattice's layout: [lx][37][ly]
 // for the column layout (population stride below column stride), [37][lx][ly]
 // for SoA.
@@ -114,10 +145,9 @@ __global__ __launch_bounds__(kThreads) void k_fused(const S* __restrict__ src,
   int x, y;
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
   const long long site = padded<S>(g, x + HX, y + g.hy);
-  using V = reg_t<A>;
-  V f[Q];
-  gather<S, V>(src, g, site, f);
-  if (on_wall_rows(g, y)) wall_site<V>(f, y, g.ly, P.th_bottom, P.th_top, P.rho_ref);
+  A f[Q];
+  gather<S, A>(src, g, site, f);
+  if (on_wall_rows(g, y)) wall_site<A>(f, y, g.ly, P.th_bottom, P.th_top, P.rho_ref);
   const Tape4 m = collide<A, kReg>(f, P);
   if (kTape) {
     const long long S2 = (long long)g.lx * g.ly, s = (long long)x * g.ly + y;
@@ -126,9 +156,37 @@ __global__ __launch_bounds__(kThreads) void k_fused(const S* __restrict__ src,
     tape[2 * S2 + s] = m.jy;
     tape[3 * S2 + s] = m.e;
   }
-  store_site<S, V>(dst, g, site, f);
-  if (x < HX) store_site<S, V>(dst, g, site + (long long)g.lx * g.cs, f);
-  if (x >= g.lx - HX) store_site<S, V>(dst, g, site - (long long)g.lx * g.cs, f);
+  store_site<S, A>(dst, g, site, f);
+  if (x < HX) store_site<S, A>(dst, g, site + (long long)g.lx * g.cs, f);
+  if (x >= g.lx - HX) store_site<S, A>(dst, g, site - (long long)g.lx * g.cs, f);
+}
+
+// Fused step of the local-reference FP32 form: each population is rebuilt in
+// FP64 from its deviation and the reference of the site it comes from
+// (f_l = M_l(rho_s, th_s of x - e_l) + g_l), then bc, the FP32 collision and
+// the store of the new deviations and reference.  Rows beyond the walls hold
+// zeros (reference 0: M = 0), which bc replaces.
+template <bool kReg>
+__global__ __launch_bounds__(kThreads) void k_fused_local(const float* __restrict__ src,
+                                                          float* __restrict__ dst, Geom g, Phys P,
+                                                          int by, int bx, int nty, unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const long long site = padded<float>(g, x + HX, y + g.hy);
+  double f[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    const long long s = site - EX[l] * g.cs - EY[l];
+    double rho, th;
+    unpack_ref(ref_at(src, g, s), rho, th);
+    f[l] = rest_maxwellian(l, rho, th) + double(src[l * g.ps + s]);
+  }
+  if (on_wall_rows(g, y)) wall_site<double>(f, y, g.ly, P.th_bottom, P.th_top, 0.0);
+  float v[Q];
+  const unsigned ref = collide_site_local<kReg>(f, v, P);
+  store_local(dst, g, site, v, ref);
+  if (x < HX) store_local(dst, g, site + (long long)g.lx * g.cs, v, ref);
+  if (x >= g.lx - HX) store_local(dst, g, site - (long long)g.lx * g.cs, v, ref);
 }
 
 template <class S>
@@ -150,11 +208,10 @@ __global__ __launch_bounds__(kThreads) void k_collide(const S* __restrict__ src,
   int x, y;
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
   const long long site = padded<S>(g, x + HX, y + g.hy);
-  using V = reg_t<A>;
-  V f[Q];
-  load_site<S, V>(src, g, site, f);
+  A f[Q];
+  load_site<S, A>(src, g, site, f);
   collide<A, kReg>(f, P);
-  store_site<S, V>(dst, g, site, f);
+  store_site<S, A>(dst, g, site, f);
 }
 
 // bc on the six wall rows, in place; one thread per (x, wall row).
@@ -180,7 +237,7 @@ template <class S>
 __global__ __launch_bounds__(kThreads) void k_halo_x(S* __restrict__ buf, Geom g) {
   const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
   const long long per_l = 6LL * g.ny;
-  if (i >= per_l * Q) return;
+  if (i >= per_l * g.np) return;
   const int l = int(i / per_l);
   const int c = int((i % per_l) / g.ny), Y = int(i % g.ny);
   const int Xd = c < 3 ? c : g.lx + c;
@@ -193,7 +250,7 @@ template <class S>
 __global__ __launch_bounds__(kThreads) void k_halo_y(S* __restrict__ buf, Geom g) {
   const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
   const long long per_l = 6LL * g.nx;
-  if (i >= per_l * Q) return;
+  if (i >= per_l * g.np) return;
   const int l = int(i / per_l);
   const int X = int((i % per_l) / 6), r = int(i % 6);
   const int Yd = r < 3 ? g.hy - 3 + r : g.hy + g.ly + (r - 3);
@@ -228,18 +285,43 @@ __global__ __launch_bounds__(kThreads) void k_init_feq(S* __restrict__ dst,
   store_site<S, A>(dst, g, padded<S>(g, x + HX, y + g.hy), f);
 }
 
-// Eq. (2) in FP64 from the stored (possibly shifted FP32) populations.
-template <class S>
+// f = f^eq(rho0, u0, T0) in the local-reference form.
+__global__ __launch_bounds__(kThreads) void k_init_local(float* __restrict__ dst,
+                                                        const double* __restrict__ rho,
+                                                        const double* __restrict__ ux,
+                                                        const double* __restrict__ uy,
+                                                        const double* __restrict__ T, Geom g,
+                                                        int by, int bx, int nty, unsigned nb) {
+  int x, y;
+  if (!site_of(g, by, bx, nty, nb, x, y)) return;
+  const long long s = (long long)x * g.ly + y;
+  double aeq[5][5];
+  equilibrium_coeffs(rho[s], ux[s], uy[s], T[s] - 1.0, aeq);
+  double f[Q];
+  reconstruct<double>(aeq, f);
+  float v[Q];
+  const unsigned ref = encode_site(f, v);
+  store_local(dst, g, padded<float>(g, x + HX, y + g.hy), v, ref);
+}
+
+// Eq. (2) in FP64 from the stored populations (FP64, shifted FP32 or the
+// local-reference form).
+template <class S, class A>
 __device__ __forceinline__ Macro site_macro(const S* __restrict__ src, const Geom& g,
                                             long long site, double rho_ref) {
   double f[Q];
-  load_site<S, double>(src, g, site, f);
+  if constexpr (is_local<A>) {
+    load_local(src, g, site, f);
+    rho_ref = 0.0;
+  } else {
+    load_site<S, double>(src, g, site, f);
+  }
   double a[5][5];
   project<double>(f, a);
   return macro_from(rho_ref + a[0][0], a[1][0], a[0][1], a[2][0], a[0][2]);
 }
 
-template <class S>
+template <class S, class A>
 __global__ __launch_bounds__(kThreads) void k_moments(const S* __restrict__ src,
                                                       double* __restrict__ rho,
                                                       double* __restrict__ ux,
@@ -248,7 +330,7 @@ __global__ __launch_bounds__(kThreads) void k_moments(const S* __restrict__ src,
                                                       int by, int bx, int nty, unsigned nb) {
   int x, y;
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
-  const Macro m = site_macro<S>(src, g, padded<S>(g, x + HX, y + g.hy), P.rho_ref);
+  const Macro m = site_macro<S, A>(src, g, padded<S>(g, x + HX, y + g.hy), P.rho_ref);
   const long long s = (long long)x * g.ly + y;
   if (rho) rho[s] = m.rho;
   if (ux) ux[s] = m.ux;
@@ -256,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void k_moments(const S* __restrict__ src,
   if (T) T[s] = 1.0 + m.th;
 }
 
-template <class S>
+template <class S, class A>
 __global__ __launch_bounds__(kThreads) void k_check(const S* __restrict__ src,
                                                     unsigned int* __restrict__ flag, Geom g,
                                                     Phys P, int by, int bx, int nty,
@@ -265,9 +347,16 @@ __global__ __launch_bounds__(kThreads) void k_check(const S* __restrict__ src,
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
   const long long site = padded<S>(g, x + HX, y + g.hy);
   bool bad = false;
+  if constexpr (is_local<A>) {
+    double f[Q];
+    load_local(src, g, site, f);
 #pragma unroll
-  for (int l = 0; l < Q; ++l) bad |= !isfinite(double(src[l * g.ps + site]));
-  const Macro m = site_macro<S>(src, g, site, P.rho_ref);
+    for (int l = 0; l < Q; ++l) bad |= !isfinite(f[l]);
+  } else {
+#pragma unroll
+    for (int l = 0; l < Q; ++l) bad |= !isfinite(double(src[l * g.ps + site]));
+  }
+  const Macro m = site_macro<S, A>(src, g, site, P.rho_ref);
   bad |= !(m.rho > 0.0) || !(1.0 + m.th > 0.0);
   if (bad) atomicAdd(flag, 1u);
 }
@@ -310,17 +399,26 @@ __global__ __launch_bounds__(kThreads) void k_unpack(const S* __restrict__ compa
   if (c.in) __builtin_nontemporal_store(compact[c.compact], &padded_buf[c.padded]);
 }
 
-template <class S>
+template <class S, class A>
 __global__ __launch_bounds__(kThreads) void k_populations_f64(const S* __restrict__ padded_buf,
                                                               double* __restrict__ out, Geom g,
                                                               double rho_ref, unsigned nyb) {
   const CompactSite c = compact_site(g, nyb);
   if (!c.in) return;
-  double w = 0.0;
+  if constexpr (is_local<A>) {
+    double rho, th, m = 0.0;
+    unpack_ref(ref_at(padded_buf, g, c.padded - c.l * g.ps), rho, th);
 #pragma unroll
-  for (int k = 0; k < Q; ++k)
-    if (k == c.l) w = W[k];
-  out[c.compact] = double(padded_buf[c.padded]) + rho_ref * w;
+    for (int k = 0; k < Q; ++k)
+      if (k == c.l) m = rest_maxwellian(k, rho, th);
+    out[c.compact] = m + double(padded_buf[c.padded]);
+  } else {
+    double w = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (k == c.l) w = W[k];
+    out[c.compact] = double(padded_buf[c.padded]) + rho_ref * w;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_zero(unsigned int* __restrict__ p, long long n) {
@@ -354,7 +452,7 @@ __global__ __launch_bounds__(kThreads) void k_loss_ke(const double* __restrict__
   const bool in = site_of(g, by, bx, nty, nb, x, y);
   double ke = 0.0;
   if (in) {
-    const Macro m = site_macro<double>(src, g, padded<double>(g, x + HX, y + g.hy), 0.0);
+    const Macro m = site_macro<double, double>(src, g, padded<double>(g, x + HX, y + g.hy), 0.0);
     const double u2 = m.ux * m.ux + m.uy * m.uy;
     ke = 0.5 * m.rho * u2;
     if (lambda) {
@@ -583,7 +681,7 @@ template <class S>
 __global__ __launch_bounds__(kThreads) void k_zero_pad_rows(S* __restrict__ buf, Geom g) {
   const int pad = g.ny - g.ly;  // hy rows below, ny - ly - hy above
   const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
-  const long long n = (long long)Q * g.nx * pad;
+  const long long n = (long long)g.np * g.nx * pad;
   if (i >= n) return;
   const int r = int(i % pad);
   const long long lx_ = i / pad;
@@ -619,7 +717,7 @@ __global__ __launch_bounds__(kThreads) void k_init_adjoint(
 
 // partial[c][k][y] = sum over the columns of chunk c of the k-th per-site
 // observable at row y: rho, u_x, u_y, T, rho |u|^2 / 2, rho T.
-template <class S>
+template <class S, class A>
 __global__ __launch_bounds__(kThreads) void k_obs_rows(const S* __restrict__ src,
                                                        double* __restrict__ partial, Geom g,
                                                        Phys P, int nchunks) {
@@ -629,11 +727,7 @@ __global__ __launch_bounds__(kThreads) void k_obs_rows(const S* __restrict__ src
   const int x0 = int((long long)g.lx * c / nchunks), x1 = int((long long)g.lx * (c + 1) / nchunks);
   double acc[kObservables] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int x = x0; x < x1; ++x) {
-    double f[Q];
-    load_site<S, double>(src, g, (long long)(x + HX) * g.cs + (y + g.hy), f);
-    double a[5][5];
-    project<double>(f, a);
-    const Macro m = macro_from(P.rho_ref + a[0][0], a[1][0], a[0][1], a[2][0], a[0][2]);
+    const Macro m = site_macro<S, A>(src, g, (long long)(x + HX) * g.cs + (y + g.hy), P.rho_ref);
     const double T = 1.0 + m.th;
     acc[0] += m.rho;
     acc[1] += m.ux;
@@ -700,10 +794,9 @@ unsigned grid_1d(long long n) { return unsigned((n + kThreads - 1) / kThreads); 
 
 // Calls fn(S{}, A{}) with the storage type S and the arithmetic type A of a
 // precision mode -> (storage type, accumulation type): FP64 storage and
-// collision; FP32 storage with the FP64 collision; FP32 storage with the
-// plain FP32 collision; FP32 storage with the FP32 collision about the local
-// rest Maxwellian (collide_site_ref).  Moments, equilibrium coefficients and
-// bc are FP64 in every mode.
+// collision; shifted FP32 storage with the FP64 collision; shifted FP32
+// storage with FP32 Hermite sums; the local-reference FP32 form (LocalRef).
+// Moments, equilibrium coefficients and bc are FP64 in every mode.
 template <class Fn>
 hipError_t by_precision(int prec, Fn fn) {
   if (prec == kF64)
@@ -713,7 +806,7 @@ hipError_t by_precision(int prec, Fn fn) {
   else if (prec == kF32ShiftedF32Sum)
     fn(float{}, float{});
   else
-    fn(float{}, F32Ref{});
+    fn(float{}, LocalRef{});
   return hipGetLastError();
 }
 
@@ -727,7 +820,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 }
 
 hipError_t launch_halo(void* buf, const Geom& g, int prec, hipStream_t s) {
-  const long long nx_el = 6LL * g.ny * Q, ny_el = 6LL * g.nx * Q;
+  const long long nx_el = 6LL * g.ny * g.np, ny_el = 6LL * g.nx * g.np;
   return by_precision(prec, [&](auto sv, auto) {
     using S = decltype(sv);
     hipLaunchKernelGGL(k_halo_x<S>, dim3(grid_1d(nx_el)), dim3(kThreads), 0, s,
@@ -748,7 +841,14 @@ hipError_t launch_fused(const void* src, void* dst, const Geom& g, const Phys& p
     const S* a = static_cast<const S*>(src);
     S* b = static_cast<S*>(dst);
     const dim3 grid(t.nb), block(kThreads);
-    if (regularize && tape)
+    if constexpr (is_local<A>) {
+      if (regularize)
+        hipLaunchKernelGGL(k_fused_local<true>, grid, block, 0, s, a, b, g, p, t.by, t.bx, t.nty,
+                           t.nb);
+      else
+        hipLaunchKernelGGL(k_fused_local<false>, grid, block, 0, s, a, b, g, p, t.by, t.bx,
+                           t.nty, t.nb);
+    } else if (regularize && tape)
       hipLaunchKernelGGL((k_fused<S, A, true, true>), grid, block, 0, s, a, b, g, p, tape, t.by,
                          t.bx, t.nty, t.nb);
     else if (regularize)
@@ -791,7 +891,9 @@ hipError_t launch_collide(const void* src, void* dst, const Geom& g, const Phys&
     using A = decltype(av);
     const S* a = static_cast<const S*>(src);
     S* b = static_cast<S*>(dst);
-    if (regularize)
+    if constexpr (is_local<A>)
+      return;  // the local-reference form has no split collide (lb_api rejects it)
+    else if (regularize)
       hipLaunchKernelGGL((k_collide<S, A, true>), dim3(t.nb), dim3(kThreads), 0, s, a, b, g, p,
                          t.by, t.bx, t.nty, t.nb);
     else
@@ -804,19 +906,23 @@ hipError_t launch_init_feq(void* dst, const double* rho, const double* ux, const
                            const double* T, const Geom& g, const Phys& p, int prec,
                            hipStream_t s) {
   const Tiling t = make_tiling(g.lx, g.ly);
-  return by_precision(prec, [&](auto sv, auto) {
+  return by_precision(prec, [&](auto sv, auto av) {
     using S = decltype(sv);
-    hipLaunchKernelGGL((k_init_feq<S, double>), dim3(t.nb), dim3(kThreads), 0, s,
-                       static_cast<S*>(dst), rho, ux, uy, T, g, p, t.by, t.bx, t.nty, t.nb);
+    if constexpr (is_local<decltype(av)>)
+      hipLaunchKernelGGL(k_init_local, dim3(t.nb), dim3(kThreads), 0, s, static_cast<float*>(dst),
+                         rho, ux, uy, T, g, t.by, t.bx, t.nty, t.nb);
+    else
+      hipLaunchKernelGGL((k_init_feq<S, double>), dim3(t.nb), dim3(kThreads), 0, s,
+                         static_cast<S*>(dst), rho, ux, uy, T, g, p, t.by, t.bx, t.nty, t.nb);
   });
 }
 
 hipError_t launch_moments(const void* src, double* rho, double* ux, double* uy, double* T,
                           const Geom& g, const Phys& p, int prec, hipStream_t s) {
   const Tiling t = make_tiling(g.lx, g.ly);
-  return by_precision(prec, [&](auto sv, auto) {
+  return by_precision(prec, [&](auto sv, auto av) {
     using S = decltype(sv);
-    hipLaunchKernelGGL(k_moments<S>, dim3(t.nb), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((k_moments<S, decltype(av)>), dim3(t.nb), dim3(kThreads), 0, s,
                        static_cast<const S*>(src), rho, ux, uy, T, g, p, t.by, t.bx, t.nty,
                        t.nb);
   });
@@ -829,14 +935,14 @@ struct CompactGrid {
   unsigned nyb;
 };
 
-CompactGrid compact_grid(const Geom& g) {
+CompactGrid compact_grid(const Geom& g, int planes) {
   const unsigned nyb = unsigned((g.ly + kThreads - 1) / kThreads);
-  return {dim3(unsigned(g.lx) * nyb, Q), nyb};
+  return {dim3(unsigned(g.lx) * nyb, unsigned(planes)), nyb};
 }
 
 hipError_t launch_pack(const void* padded_buf, void* compact, const Geom& g, int prec,
                        hipStream_t s) {
-  const CompactGrid cg = compact_grid(g);
+  const CompactGrid cg = compact_grid(g, g.np);
   return by_precision(prec, [&](auto sv, auto) {
     using S = decltype(sv);
     hipLaunchKernelGGL(k_pack<S>, cg.grid, dim3(kThreads), 0, s,
@@ -846,7 +952,7 @@ hipError_t launch_pack(const void* padded_buf, void* compact, const Geom& g, int
 
 hipError_t launch_unpack(const void* compact, void* padded_buf, const Geom& g, int prec,
                          hipStream_t s) {
-  const CompactGrid cg = compact_grid(g);
+  const CompactGrid cg = compact_grid(g, g.np);
   return by_precision(prec, [&](auto sv, auto) {
     using S = decltype(sv);
     hipLaunchKernelGGL(k_unpack<S>, cg.grid, dim3(kThreads), 0, s,
@@ -856,10 +962,10 @@ hipError_t launch_unpack(const void* compact, void* padded_buf, const Geom& g, i
 
 hipError_t launch_populations_f64(const void* padded_buf, double* out, const Geom& g,
                                   const Phys& p, int prec, hipStream_t s) {
-  const CompactGrid cg = compact_grid(g);
-  return by_precision(prec, [&](auto sv, auto) {
+  const CompactGrid cg = compact_grid(g, Q);
+  return by_precision(prec, [&](auto sv, auto av) {
     using S = decltype(sv);
-    hipLaunchKernelGGL(k_populations_f64<S>, cg.grid, dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((k_populations_f64<S, decltype(av)>), cg.grid, dim3(kThreads), 0, s,
                        static_cast<const S*>(padded_buf), out, g, p.rho_ref, cg.nyb);
   });
 }
@@ -867,9 +973,9 @@ hipError_t launch_populations_f64(const void* padded_buf, double* out, const Geo
 hipError_t launch_check(const void* src, unsigned int* flag, const Geom& g, const Phys& p,
                         int prec, hipStream_t s) {
   const Tiling t = make_tiling(g.lx, g.ly);
-  return by_precision(prec, [&](auto sv, auto) {
+  return by_precision(prec, [&](auto sv, auto av) {
     using S = decltype(sv);
-    hipLaunchKernelGGL(k_check<S>, dim3(t.nb), dim3(kThreads), 0, s, static_cast<const S*>(src),
+    hipLaunchKernelGGL((k_check<S, decltype(av)>), dim3(t.nb), dim3(kThreads), 0, s, static_cast<const S*>(src),
                        flag, g, p, t.by, t.bx, t.nty, t.nb);
   });
 }
@@ -880,9 +986,9 @@ hipError_t launch_observables(const void* src, double* partial, double* profiles
                               double* scalars, const Geom& g, const Phys& p, int prec,
                               double t_bottom, double t_top, hipStream_t s) {
   const int nc = observable_chunks(g);
-  hipError_t e = by_precision(prec, [&](auto sv, auto) {
+  hipError_t e = by_precision(prec, [&](auto sv, auto av) {
     using S = decltype(sv);
-    hipLaunchKernelGGL(k_obs_rows<S>, dim3(grid_1d(g.ly), nc), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((k_obs_rows<S, decltype(av)>), dim3(grid_1d(g.ly), nc), dim3(kThreads), 0, s,
                        static_cast<const S*>(src), partial, g, p, nc);
   });
   if (e != hipSuccess) return e;
@@ -948,7 +1054,7 @@ hipError_t launch_adjoint_gather(const double* mu, double* lam, const Geom& g, h
 }
 
 hipError_t launch_zero_pad_rows(void* buf, const Geom& g, int prec, hipStream_t s) {
-  const long long n = (long long)Q * g.nx * (g.ny - g.ly);
+  const long long n = (long long)g.np * g.nx * (g.ny - g.ly);
   return by_precision(prec, [&](auto sv, auto) {
     using S = decltype(sv);
     hipLaunchKernelGGL(k_zero_pad_rows<S>, dim3(grid_1d(n)), dim3(kThreads), 0, s,

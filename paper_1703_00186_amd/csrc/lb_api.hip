@@ -104,12 +104,13 @@ Geom make_geom(const lb_lattice& lat) {
   g.hy = per_line;  // physical row 0 starts 256-byte aligned
   g.ny = int(round_up(size_t(lat.ly) + 2 * size_t(g.hy), size_t(per_line)));
   g.walls = lat.ybc == LB_Y_WALLS;
+  g.np = lat.precision == LB_FP32_COLLIDE ? d2q37::kLocalPlanes : d2q37::Q;
   if (lat.layout == LB_LAYOUT_SOA) {
     g.ps = (long long)g.nx * g.ny;
     g.cs = g.ny;
   } else {
     g.ps = g.ny;
-    g.cs = (long long)d2q37::Q * g.ny;
+    g.cs = (long long)g.np * g.ny;
   }
   return g;
 }
@@ -122,12 +123,26 @@ Phys make_phys(const lb_params& par, int prec) {
   p.dtheta = par.tau * (1.0 - par.tau) * (par.gx * par.gx + par.gy * par.gy) / 2.0;
   p.th_bottom = par.t_bottom - 1.0;
   p.th_top = par.t_top - 1.0;
-  p.rho_ref = prec == LB_FP64 ? 0.0 : par.rho_ref;
+  p.rho_ref = (prec == LB_FP64 || prec == LB_FP32_COLLIDE) ? 0.0 : par.rho_ref;
   return p;
 }
 
 size_t buffer_bytes(const Geom& g, int prec) {
-  return round_up(size_t(d2q37::Q) * size_t(g.nx) * size_t(g.ny) * elem_bytes(prec), kAlign);
+  return round_up(size_t(g.np) * size_t(g.nx) * size_t(g.ny) * elem_bytes(prec), kAlign);
+}
+
+// The local-reference form rebuilds a population from the reference of the
+// site it comes from, which only the fused step has at hand: no split path.
+int check_kernel(int prec, const lb_params& par) {
+  if (prec == LB_FP32_COLLIDE && par.kernel != LB_KERNEL_FUSED)
+    return fail(LB_E_ARG, "LB_FP32_COLLIDE runs the fused kernel only%s");
+  return LB_OK;
+}
+
+int no_split_stage(lb_ctx* ctx, const char* what) {
+  if (ctx->prec == LB_FP32_COLLIDE)
+    return fail(LB_E_STATE, "%s is not available for LB_FP32_COLLIDE (fused kernel only)", what);
+  return LB_OK;
 }
 
 size_t partial_bytes(const Geom& g) {
@@ -215,6 +230,8 @@ int lb_workspace_bytes(const lb_lattice* lat, const lb_params* par, size_t* byte
   if (rc) return rc;
   rc = check_params(par);
   if (rc) return rc;
+  rc = check_kernel(lat->precision, *par);
+  if (rc) return rc;
   if (!bytes) return fail(LB_E_ARG, "bytes is NULL%s");
   const Geom g = make_geom(*lat);
   *bytes = 2 * buffer_bytes(g, lat->precision) + partial_bytes(g) + observable_bytes(g) + kAlign;
@@ -291,6 +308,8 @@ int lb_set_params(lb_ctx* ctx, const lb_params* par) {
   if (rc) return rc;
   rc = check_params(par);
   if (rc) return rc;
+  rc = check_kernel(ctx->prec, *par);
+  if (rc) return rc;
   if (ctx->prec != LB_FP64 && par->rho_ref != ctx->par.rho_ref)
     return fail(LB_E_ARG, "rho_ref cannot change after lb_init%s");
   ctx->par = *par;
@@ -351,6 +370,8 @@ int lb_halo(lb_ctx* ctx) {
 int lb_propagate(lb_ctx* ctx) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
+  rc = no_split_stage(ctx, "lb_propagate");
+  if (rc) return rc;
   LB_HIP(d2q37::launch_propagate(ctx->A, ctx->B, ctx->g, ctx->prec, ctx->stream), "propagate");
   return LB_OK;
 }
@@ -358,12 +379,16 @@ int lb_propagate(lb_ctx* ctx) {
 int lb_bc(lb_ctx* ctx) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
+  rc = no_split_stage(ctx, "lb_bc");
+  if (rc) return rc;
   LB_HIP(d2q37::launch_bc(ctx->B, ctx->g, ctx->p, ctx->prec, ctx->stream), "bc");
   return LB_OK;
 }
 
 int lb_collide(lb_ctx* ctx) {
   int rc = check_ctx(ctx);
+  if (rc) return rc;
+  rc = no_split_stage(ctx, "lb_collide");
   if (rc) return rc;
   LB_HIP(d2q37::launch_collide(ctx->B, ctx->A, ctx->g, ctx->p, ctx->prec, ctx->par.regularize,
                                ctx->stream),
@@ -375,6 +400,8 @@ int lb_collide(lb_ctx* ctx) {
 int lb_get_scratch(lb_ctx* ctx, void* f) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
+  rc = no_split_stage(ctx, "lb_get_scratch");
+  if (rc) return rc;
   if (!f) return fail(LB_E_ARG, "f is NULL%s");
   LB_HIP(d2q37::launch_pack(ctx->B, f, ctx->g, ctx->prec, ctx->stream), "get_scratch");
   return LB_OK;
@@ -382,6 +409,8 @@ int lb_get_scratch(lb_ctx* ctx, void* f) {
 
 int lb_set_scratch(lb_ctx* ctx, const void* f) {
   int rc = check_ctx(ctx);
+  if (rc) return rc;
+  rc = no_split_stage(ctx, "lb_set_scratch");
   if (rc) return rc;
   if (!f) return fail(LB_E_ARG, "f is NULL%s");
   LB_HIP(d2q37::launch_unpack(f, ctx->B, ctx->g, ctx->prec, ctx->stream), "set_scratch");

@@ -191,10 +191,25 @@ class LB:
         """torch dtype of the stored state: float64, or float32 for the FP32 forms."""
         return torch.float64 if self.precision == "fp64" else torch.float32
 
+    @property
+    def state_planes(self) -> int:
+        """Planes of the compact state: 37 populations, plus the packed
+        reference (two FP16 numbers per site) in the local-reference FP32
+        form ("fp32c")."""
+        return Q + 1 if self.precision == "fp32c" else Q
+
+    @property
+    def state_shape(self):
+        return (self.state_planes, self.lx, self.ly)
+
     def new_populations(self, dtype=None) -> torch.Tensor:
         """An uninitialised [37, lx, ly] device tensor (state dtype by default)."""
         return torch.empty((Q, self.lx, self.ly), dtype=dtype or self.state_dtype,
                            device=self.device)
+
+    def new_state(self) -> torch.Tensor:
+        """An uninitialised device tensor of the compact state's shape and dtype."""
+        return torch.empty(self.state_shape, dtype=self.state_dtype, device=self.device)
 
     # adjoint populations are stored in the lattice's layout: [lx, 37, ly]
     # (column) or [37, lx, ly] (SoA); lambda_view gives the [37, lx, ly] view
@@ -283,23 +298,26 @@ class LB:
             raise ValueError("%s must be a contiguous %s tensor of shape %s on %s"
                              % (what, dtype, tuple(shape), self.device))
 
-    def _state_arg(self, f, what: str) -> torch.Tensor:
-        """A [37, lx, ly] array in the state's dtype (FP64, or the shifted FP32
-        values), moved to the device; no dtype conversion."""
+    def _state_arg(self, f, what: str, shape=None) -> torch.Tensor:
+        """An array of the compact state's shape and dtype (FP64, the shifted
+        FP32 values, or the local-reference form's deviations and packed
+        references), moved to the device; no dtype conversion."""
+        shape = tuple(shape or self.state_shape)
         t = torch.as_tensor(f)
-        if tuple(t.shape) != (Q, self.lx, self.ly) or t.dtype != self.state_dtype:
-            raise ValueError("%s must be %s of shape %s" % (what, self.state_dtype,
-                                                            (Q, self.lx, self.ly)))
+        if tuple(t.shape) != shape or t.dtype != self.state_dtype:
+            raise ValueError("%s must be %s of shape %s" % (what, self.state_dtype, shape))
         return t.to(self.device).contiguous()
 
     def get_state(self, out=None) -> torch.Tensor:
-        """The state in compact [37, lx, ly] form, in the state dtype (FP32 forms:
-        the shifted values f - w rho_ref); `out` may be given to reuse a tensor."""
+        """The state in compact form, in the state dtype: [37, lx, ly] (FP64, or
+        the shifted FP32 values f - w rho_ref), or [38, lx, ly] FP32 in the
+        local-reference form (deviations, then the packed references); `out`
+        may be given to reuse a tensor."""
         self._sync_stream()
         if out is None:
-            out = self.new_populations()
+            out = self.new_state()
         else:
-            self._expect(out, (Q, self.lx, self.ly), self.state_dtype, "out")
+            self._expect(out, self.state_shape, self.state_dtype, "out")
         _check(self.lib.lb_get_state(self.ctx, _ptr(out)))
         return out
 
@@ -347,7 +365,7 @@ class LB:
     def set_scratch(self, f: torch.Tensor):
         """Replaces the scratch buffer by f (compact form, state dtype)."""
         self._sync_stream()
-        f = self._state_arg(f, "scratch")
+        f = self._state_arg(f, "scratch", (Q, self.lx, self.ly))
         _check(self.lib.lb_set_scratch(self.ctx, _ptr(f)))
 
     # -- in-situ observables ------------------------------------------------

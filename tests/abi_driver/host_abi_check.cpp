@@ -36,8 +36,13 @@ void check_context(int precision, int layout, int kernel, int ybc) {
   lb_lattice lat = {lx, ly, precision, ybc, layout, 0};
   lb_params par = {0.7, 1e-4, -1e-4, 1.5, 0.5, 1.0, 1, kernel, 0, 0};
   size_t need = 0;
+  const bool local = precision == LB_FP32_COLLIDE;
+  if (local && kernel != LB_KERNEL_FUSED) {  // fused kernel only
+    EXPECT(lb_workspace_bytes(&lat, &par, &need) == LB_E_ARG);
+    return;
+  }
   EXPECT(lb_workspace_bytes(&lat, &par, &need) == LB_OK);
-  EXPECT(need >= 2 * 37 * S * (precision == LB_FP64 ? 8 : 4));
+  EXPECT(need >= 2 * (local ? 38 : 37) * S * (precision == LB_FP64 ? 8 : 4));
   void* ws = std::aligned_alloc(256, round256(need) + 256);
   std::vector<double> fields(4 * S, 1.0), out(4 * S), lam_a(37 * S), lam_b(37 * S);
   std::vector<double> tape(3 * 4 * S), prof(6 * ly), sc(4), series(3 * 4), pops(37 * S);
@@ -67,9 +72,11 @@ void check_context(int precision, int layout, int kernel, int ybc) {
   EXPECT(lb_get_state(ctx, state.data()) == LB_OK);
   EXPECT(lb_set_state(ctx, state.data()) == LB_OK);
   EXPECT(lb_get_populations(ctx, pops.data()) == LB_OK);
-  EXPECT(lb_halo(ctx) == LB_OK && lb_propagate(ctx) == LB_OK && lb_bc(ctx) == LB_OK &&
-         lb_collide(ctx) == LB_OK);
-  EXPECT(lb_get_scratch(ctx, state.data()) == LB_OK && lb_set_scratch(ctx, state.data()) == LB_OK);
+  const int split_rc = local ? LB_E_STATE : LB_OK;
+  EXPECT(lb_halo(ctx) == LB_OK);
+  EXPECT(lb_propagate(ctx) == split_rc && lb_bc(ctx) == split_rc && lb_collide(ctx) == split_rc);
+  EXPECT(lb_get_scratch(ctx, state.data()) == split_rc &&
+         lb_set_scratch(ctx, state.data()) == split_rc);
   EXPECT(lb_observables(ctx, prof.data(), sc.data()) == LB_OK);
   EXPECT(lb_observables(ctx, nullptr, sc.data()) == LB_OK);
   EXPECT(lb_run_observed(ctx, 12, 4, series.data()) == LB_OK);
@@ -87,6 +94,8 @@ void check_context(int precision, int layout, int kernel, int ybc) {
   p2 = par;
   p2.kernel = kernel == LB_KERNEL_FUSED ? LB_KERNEL_SPLIT : LB_KERNEL_FUSED;
   p2.regularize = 0;
+  EXPECT(lb_set_params(ctx, &p2) == (local ? LB_E_ARG : LB_OK));
+  p2.kernel = kernel;
   EXPECT(lb_set_params(ctx, &p2) == LB_OK);
   EXPECT(lb_step(ctx, 2) == LB_OK);
 

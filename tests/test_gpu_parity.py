@@ -100,16 +100,36 @@ def test_collide(layout, regularize):
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+@pytest.fixture(scope="module")
+def extended_256x128_50():
+    """The parity lattice after 50 steps in the oracle's extended-precision
+    run (long double, model constants rounded from the binary128 solve): the
+    reference against which FP64 rounding is measured.  Also the FP64
+    oracle's populations and its own error against that reference."""
+    lx, ly = 256, 128
+    fields = workload.rt_fields(lx, ly, seed=170301)[:4]
+    f0 = oracle.init_feq(*fields)
+    ext = oracle.run_moments_extended(f0, oparams(), 50)
+    f64 = oracle.run(f0, oparams(), 50)
+    return ext, f64, field_errors(oracle.moments(f64), ext)
+
+
 @pytest.mark.parametrize("kernel", ["fused", "split"])
 @pytest.mark.parametrize("layout", ["soa", "column"])
-def test_rt_256x128_50_steps(kernel, layout):
-    """256 x 128 Rayleigh-Taylor, 50 steps: every field within 1e-12."""
+def test_rt_256x128_50_steps(kernel, layout, extended_256x128_50):
+    """256 x 128 Rayleigh-Taylor, 50 steps: every field (u as max|du| / max|u|,
+    max and rms) within 1e-12 of the extended-precision oracle run; the
+    populations within 1e-12 of the FP64 oracle's.  (The FP64 oracle's own
+    distance from the extended run is printed: its f^eq polynomial and BGK
+    sums carry more rounding than the GPU's Hermite-space collision.)"""
     lx, ly = 256, 128
+    ext, f_ref, oracle_own = extended_256x128_50
     lb, fields = make(lx, ly, kernel=kernel, layout=layout)
     lb.step(50)
     m_gpu = [host(t) for t in lb.moments()]
-    f_ref = oracle.run(oracle.init_feq(*fields), oparams(), 50)
-    errs = field_errors(m_gpu, oracle.moments(f_ref))
+    errs = field_errors(m_gpu, ext)
+    print("GPU vs extended oracle:", errs)
+    print("FP64 oracle vs extended oracle:", oracle_own)
     assert worst(errs) <= 1e-12, errs
     f_gpu = host(lb.populations())
     assert np.abs(f_gpu - f_ref).max() <= 1e-12 * np.abs(f_ref).max()
@@ -119,8 +139,9 @@ def test_rt_uniform_density_init():
     lx, ly = 256, 128
     lb, fields = make(lx, ly, mode="uniform")
     lb.step(50)
-    f_ref = oracle.run(oracle.init_feq(*fields), oparams(), 50)
-    errs = field_errors([host(t) for t in lb.moments()], oracle.moments(f_ref))
+    ext = oracle.run_moments_extended(oracle.init_feq(*fields), oparams(), 50)
+    errs = field_errors([host(t) for t in lb.moments()], ext)
+    print("uniform init, GPU vs extended oracle:", errs)
     assert worst(errs) <= 1e-12, errs
 
 
@@ -212,7 +233,13 @@ def test_rest_state_at_the_wall_temperature_is_a_fixed_point(kernel, T_wall):
     assert np.abs(f - f0).max() <= 1e-13 * np.abs(f0).max()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+def bits(t):
+    """The raw bits of a state tensor (the packed FP16 references of the
+    local-reference form need not be valid FP32 numbers)."""
+    return t.view(torch.int64 if t.dtype == torch.float64 else torch.int32)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp32c"])
 def test_checkpoint_file_round_trip(tmp_path, precision):
     """save_checkpoint / load_checkpoint: the resumed run is bit-identical."""
     lb, fields = make(48, 40, precision=precision)
@@ -225,7 +252,7 @@ def test_checkpoint_file_round_trip(tmp_path, precision):
     meta = other.load_checkpoint(path)
     assert meta["precision"] == precision
     other.step(9)
-    assert torch.equal(other.get_state(), after)
+    assert torch.equal(bits(other.get_state()), bits(after))
     wrong, _ = make(40, 48, precision=precision)
     with pytest.raises(ValueError):
         wrong.load_checkpoint(path)

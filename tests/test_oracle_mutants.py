@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "d2q37_oracle.cpp")
 PINS = ["tests/test_oracle_model.py", "tests/test_oracle_collide.py",
         "tests/test_oracle_stream.py", "tests/test_oracle_physics.py",
-        "tests/test_oracle_derived.py"]
+        "tests/test_oracle_derived.py", "tests/test_oracle_extended.py"]
 
 MUTANTS = {
     "equilibrium_drops_theta_squared": (
@@ -30,8 +30,9 @@ MUTANTS = {
     "forcing_temperature_sign": ("tau * (1.0 - tau) * (P.gx", "tau * (1.0 + tau) * (P.gx"),
     "projection_factorial_index": (
         "/ (factorial(p) * factorial(q))", "/ (factorial(p) * factorial(p))"),
-    "projection_transposed_hermite": ("a += h[m] * M.H[m][p][q];", "a += h[m] * M.H[m][q][p];"),
-    "hermite_2_missing_constant": ("case 2: return x * x - 1.0;", "case 2: return x * x;"),
+    "projection_transposed_hermite": (
+        "a += h[m] * Consts<S>::H(m, p, q);", "a += h[m] * Consts<S>::H(m, q, p);"),
+    "hermite_2_missing_constant": ("case 2: return x * x - 1;", "case 2: return x * x;"),
     "temperature_wrong_dimension": (
         "T = (e - rho * (ux * ux + uy * uy)) / (2.0 * rho);",
         "T = (e - rho * (ux * ux + uy * uy)) / (3.0 * rho);"),
@@ -40,13 +41,16 @@ MUTANTS = {
     "bc_walls_swapped": ("const S* v = (y < 3) ? vb : vt;", "const S* v = (y < 3) ? vt : vb;"),
     "bc_off_by_one_unknown": (
         "unknown[l] = (ys < 0 || ys >= ly);", "unknown[l] = (ys < 0 || ys > ly);"),
-    "bgk_rate_inverted": (
-        "h[l] = (1.0 - 1.0 / tau) * ft[l] + feq[l] / tau;",
-        "h[l] = (1.0 - tau) * ft[l] + feq[l] * tau;"),
+    "bgk_rate_inverted": ("const S omega = S(1.0) / S(tau);", "const S omega = S(tau);"),
     "kinetic_energy_drops_half": (
         "ke += 0.5 * rho * (ux * ux + uy * uy);", "ke += rho * (ux * ux + uy * uy);"),
     "step_sites_reversed_gather": (
         "const int xs_ = wrap(x - M.cx[l], lx);", "const int xs_ = wrap(x + M.cx[l], lx);"),
+    "extended_run_fp64_weights": (
+        "static long double w(int l) { return model().wx[l]; }",
+        "static long double w(int l) { return model().w[l]; }"),
+    "bgk_weights_not_summing_to_one": (
+        "const S keep = S(1.0) - omega;", "const S keep = S(1.0 - 1.0 / 0.7000000000000001);"),
     "quadrature_redundant_condition": (
         "{4, 2}, {8, 0}, {6, 2}, {4, 4}};", "{4, 2}, {8, 0}, {6, 2}, {2, 6}};"),
 }
