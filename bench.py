@@ -30,11 +30,11 @@ Q = 37
 
 def bytes_per_site(precision: str = "fp64") -> int:
     """Algorithmic HBM bytes of one site update: read and write 37 populations
-    (8 or 4 bytes each); the local-reference FP32 form ("fp32c") also reads
-    and writes its site's packed reference (4 bytes)."""
+    (8 or 4 bytes each); the local-reference FP32 forms ("fp32c", "fp32l")
+    also read and write their site's packed reference (4 bytes)."""
     if precision == "fp64":
         return 2 * Q * 8
-    return 2 * (Q + 1) * 4 if precision == "fp32c" else 2 * Q * 4
+    return 2 * (Q + 1) * 4 if precision in ("fp32c", "fp32l") else 2 * Q * 4
 
 
 def mlups(sites: int, seconds: float) -> float:
@@ -223,6 +223,9 @@ FP32_FORMS = (
      "FP32 storage of each population's deviation from its writer site's rest Maxwellian "
      "(+ that site's FP16 density and temperature), FP32 collision (FP64 for the collision "
      "invariants, the equilibrium coefficients and a conservation correction)"),
+    ("fp32_local_fp64_collide", "fp32l",
+     "FP32 storage of each population's deviation from its writer site's rest Maxwellian "
+     "(+ that site's FP16 density and temperature), FP64 collision"),
     ("fp32_storage_fp64_collide", "fp32s", "FP32 storage of f - w rho_ref, FP64 collision"),
     ("fp32_shifted_f32sum", "fp32s_f32sum",
      "ablation: FP32 storage, the FP64 collision's Hermite sums in FP32"),
@@ -289,7 +292,7 @@ def production_leg(torch, steps: int = 200, warmup: int = 10, n_adj: int = 100,
     sites = lx * ly
     fields = workload.rt_fields(lx, ly, seed=workload.config_seed(5), mode="multimode")[:4]
     rec = {"lattice": [lx, ly], "steps_timed": steps, "warmup": warmup}
-    for prec in ("fp32c", "fp32s", "fp64"):
+    for prec in ("fp32c", "fp32l", "fp32s", "fp64"):
         torch.cuda.empty_cache()
         lb = LB(lx, ly, *fields, precision=prec)
         ws = int(lb.workspace.numel())
@@ -438,14 +441,14 @@ def _fp32_workload(args, P, torch) -> dict:
     f = workload.rt_fields(lx, ly, seed=workload.config_seed(3))[:4]
     rec = {"workload": "FP32 precision 4096x4096", "lattice": [lx, ly], "steps": n}
     ms = {}
-    for prec in ("fp64", "fp32c", "fp32s", "fp32s_f32sum"):
+    for prec in ("fp64", "fp32c", "fp32l", "fp32s", "fp32s_f32sum"):
         lb = LB(lx, ly, *f, precision=prec)
         t = time_steps(lb, n, torch)
         ms[prec] = host_moments(lb, torch)
         rec[prec] = {"MLUPS": round(mlups(lx * ly * n, t), 1)}
         del lb
         torch.cuda.empty_cache()
-    for prec in ("fp32c", "fp32s", "fp32s_f32sum"):
+    for prec in ("fp32c", "fp32l", "fp32s", "fp32s_f32sum"):
         rec[prec]["error_vs_fp64_gpu"] = field_errors(ms[prec], ms["fp64"])
         rec[prec]["ratio_vs_fp64"] = round(rec[prec]["MLUPS"] / rec["fp64"]["MLUPS"], 3)
     lxs = 256
@@ -453,7 +456,7 @@ def _fp32_workload(args, P, torch) -> dict:
     t0 = time.perf_counter()
     ref = oracle.moments(oracle.run(oracle.init_feq(*fs), P, n))
     t_or = time.perf_counter() - t0
-    for prec in ("fp32c", "fp32s", "fp32s_f32sum"):
+    for prec in ("fp32c", "fp32l", "fp32s", "fp32s_f32sum"):
         lb = LB(lxs, lxs, *fs, precision=prec)
         lb.step(n)
         rec[prec]["error_vs_oracle_256x256"] = field_errors(host_moments(lb, torch), ref)
@@ -681,7 +684,7 @@ def run_ablations(args, torch) -> list:
     f = workload.rt_fields(lx, ly, seed=workload.config_seed(2))[:4]
     speed = {}
     for layout in ("soa", "column"):
-        for prec in ("fp64", "fp32c", "fp32s"):
+        for prec in ("fp64", "fp32c", "fp32l", "fp32s"):
             for reg in (1, 0):
                 lb = LB(lx, ly, *f, precision=prec, layout=layout, regularize=reg)
                 lb.step(20)

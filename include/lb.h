@@ -59,17 +59,28 @@ extern "C" {
  *  LB_FP32_SHIFTED_F32SUM: FP32 storage, the FP64 collision's Hermite sums in
  *    FP32 (an ablation: its error grows past 1e-5 within a few hundred steps
  *    of the Rayleigh-Taylor lattice).
- *  LB_FP32_COLLIDE: FP32 storage, FP32 collision.  The Hermite projection and
- *    reconstruction run in FP32 on the deviation of the populations from the
- *    site's rest Maxwellian; FP64 is kept for the sums of the collision
- *    invariants (mass, momentum, energy), the reference Maxwellian and the
+ *  LB_FP32_COLLIDE and LB_FP32_LOCAL store each population as its FP32
+ *    deviation g_l = f_l - M_l from the rest Maxwellian
+ *    M_l = f^eq_l(rho_s, 0, 1 + th_s) of the site that collided it, and that
+ *    site's (rho_s, th_s) as two FP16 numbers in one 32-bit word (a 38th
+ *    plane); the deviation holds only the flow and the non-equilibrium part
+ *    of f, so its rounding is far below an FP32 rounding of f.  Fused kernel
+ *    only (the split stages need the source site's reference).
+ *  LB_FP32_COLLIDE: that storage with an FP32 collision: the Hermite
+ *    projection and reconstruction run in FP32 on the deviation; FP64 is kept
+ *    for the sums of the collision invariants (mass, momentum, energy), the
  *    equilibrium's Hermite coefficients (Sec. 2: the collision is a
- *    relaxation towards that equilibrium, projected on Hermite polynomials). */
+ *    relaxation towards that equilibrium, projected on Hermite polynomials)
+ *    and a correction that restores the invariants after the FP32
+ *    reconstruction.
+ *  LB_FP32_LOCAL: that storage with the FP64 collision. */
 #define LB_FP64 0                /* FP64 storage, FP64 collision           */
 #define LB_FP32_SHIFTED 1        /* FP32 storage, FP64 collision           */
 #define LB_FP32_SHIFTED_F32SUM 2 /* FP32 storage, FP32 Hermite sums        */
-#define LB_FP32_COLLIDE 3        /* FP32 storage, FP32 collision about the */
-                                 /* rest Maxwellian, FP64 invariants       */
+#define LB_FP32_COLLIDE 3        /* FP32 local-reference storage, FP32     */
+                                 /* collision, FP64 invariants             */
+#define LB_FP32_LOCAL 4          /* FP32 local-reference storage, FP64     */
+                                 /* collision                              */
 /* lb_lattice.ybc */
 #define LB_Y_WALLS 0    /* thermal walls below row 0 and above row ly-1 */
 #define LB_Y_PERIODIC 1 /* periodic y (no walls), for tests             */
@@ -108,7 +119,7 @@ typedef struct lb_ctx lb_ctx;
 
 const char* lb_last_error(void);
 /* Interface version: 4 (3: adjoint arrays in the lattice's layout and
- * lb_adjoint_run; 4: precision LB_FP32_COLLIDE). */
+ * lb_adjoint_run; 4: precisions LB_FP32_COLLIDE and LB_FP32_LOCAL). */
 int lb_version(void);
 
 /* Bytes of device workspace lb_init needs for this lattice (two padded

@@ -560,6 +560,27 @@ __device__ __forceinline__ unsigned collide_site_local(const double (&f)[Q], flo
   return ref;
 }
 
+// The FP64 collision in the local-reference storage form: f (FP64, rebuilt
+// from the stored deviations) is collided as in the FP64 form; the new
+// reference is the site's density and th = E / (2 rho) - 1 of the
+// pre-collision invariants (the collision changes E only by the forcing
+// increment), and the deviations g = f' - M(rho_s, th_s) are rounded to FP32
+// once.
+template <bool kRegularize>
+__device__ __forceinline__ unsigned collide_site_local64(double (&f)[Q], float (&g)[Q],
+                                                         const Phys& P) {
+  const Tape4 m = collide_site<double, kRegularize>(f, P);
+  const unsigned ref = pack_ref(m.rho, 0.5 * m.e / m.rho - 1.0);
+  double rs, ts;
+  unpack_ref(ref, rs, ts);
+  double mf[kFamilies];
+#pragma unroll
+  for (int k = 0; k < kFamilies; ++k) mf[k] = rest_maxwellian(kFamilyLabel[k], rs, ts);
+#pragma unroll
+  for (int l = 0; l < Q; ++l) g[l] = float(f[l] - mf[family_of(l)]);
+  return ref;
+}
+
 // Collision dispatch on the accumulation type of the FP64 and shifted FP32
 // forms (the local-reference form has kernels of its own).
 template <class A, bool kRegularize>

@@ -86,12 +86,18 @@ __device__ __forceinline__ void store_site(S* __restrict__ dst, const Geom& g, l
   for (int l = 0; l < Q; ++l) __builtin_nontemporal_store(S(f[l]), &dst[l * g.ps + site]);
 }
 
-// Accumulation-type tag of the local-reference FP32 form (populations stored
-// as FP32 deviations from the rest Maxwellian of their writer site, plus
-// that site's packed reference in plane Q; collide_site_local).
-struct LocalRef {};
+// Accumulation-type tags of the local-reference FP32 forms (populations
+// stored as FP32 deviations from the rest Maxwellian of their writer site,
+// plus that site's packed reference in plane Q), with the FP32 or the FP64
+// collision.
+template <bool kF64Collide>
+struct LocalRefT {
+  static constexpr bool f64_collide = kF64Collide;
+};
+using LocalRef = LocalRefT<false>;    // FP32 collision (collide_site_local)
+using LocalRef64 = LocalRefT<true>;   // FP64 collision (collide_site_local64)
 template <class A>
-constexpr bool is_local = std::is_same<A, LocalRef>::value;
+constexpr bool is_local = std::is_same<A, LocalRef>::value || std::is_same<A, LocalRef64>::value;
 
 // The packed reference word of padded site `site` (plane Q).
 __device__ __forceinline__ unsigned ref_at(const float* __restrict__ buf, const Geom& g,
@@ -166,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const S* __restrict__ src,
 // (f_l = M_l(rho_s, th_s of x - e_l) + g_l), then bc, the FP32 collision and
 // the store of the new deviations and reference.  Rows beyond the walls hold
 // zeros (reference 0: M = 0), which bc replaces.
-template <bool kReg>
+template <bool kReg, bool kF64Collide>
 __global__ __launch_bounds__(kThreads) void k_fused_local(const float* __restrict__ src,
                                                           float* __restrict__ dst, Geom g, Phys P,
                                                           int by, int bx, int nty, unsigned nb) {
@@ -183,8 +189,69 @@ __global__ __launch_bounds__(kThreads) void k_fused_local(const float* __restric
   }
   if (on_wall_rows(g, y)) wall_site<double>(f, y, g.ly, P.th_bottom, P.th_top, 0.0);
   float v[Q];
-  const unsigned ref = collide_site_local<kReg>(f, v, P);
+  const unsigned ref =
+      kF64Collide ? collide_site_local64<kReg>(f, v, P) : collide_site_local<kReg>(f, v, P);
   store_local(dst, g, site, v, ref);
+  if (x < HX) store_local(dst, g, site + (long long)g.lx * g.cs, v, ref);
+  if (x >= g.lx - HX) store_local(dst, g, site - (long long)g.lx * g.cs, v, ref);
+}
+
+// The same step for the column layout, with the loads and stores of the
+// tile's own columns addressed through buffer resources: one resource spans
+// the padded columns x0 .. x0 + bx + 5 that the tile's gathers read (its
+// first column is the tile's first source column), so every load is the
+// lane's 32-bit offset (shared by all populations) plus a per-population
+// scalar offset and an immediate row shift; no per-lane 64-bit address
+// arithmetic.  The lattice-wide halo double-writes keep global stores.
+constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
+constexpr int kNonTemporal = 2;           // cache policy bits of a streaming store
+
+template <bool kReg, bool kF64Collide>
+__global__ __launch_bounds__(kThreads) void k_fused_local_col(const float* __restrict__ src,
+                                                              float* __restrict__ dst, Geom g,
+                                                              Phys P, int by, int bx, int nty,
+                                                              unsigned nb) {
+  const unsigned t = tile_index(nb);
+  const int ty = int(t % unsigned(nty)), tx = int(t / unsigned(nty));
+  const int x0 = tx * bx;  // the tile's first column (workgroup-uniform)
+  const int lin = threadIdx.x;
+  const int y = ty * by + (lin % by), x = x0 + (lin / by);
+  if (x >= g.lx || y >= g.ly) return;
+  const unsigned cs = unsigned(g.cs), ps = unsigned(g.ps);
+  const long long first = (long long)x0 * g.cs;  // padded column x0 = source column x0 - 3
+  const unsigned span = unsigned(min((long long)(bx + 2 * HX) * g.cs,
+                                     (long long)g.nx * g.cs - first) * 4);
+  const __amdgpu_buffer_rsrc_t in =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(src + first), (short)0, span, kBufferWord3);
+  const unsigned Y = unsigned(y + g.hy);
+  const unsigned lane = (unsigned(x - x0) * cs + Y - 3u) * 4u;
+  double f[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    const unsigned col = unsigned(HX - EX[l]) * cs;  // source column, relative
+    const unsigned dy = unsigned(3 - EY[l]) * 4u;
+    const unsigned ref = __builtin_amdgcn_raw_buffer_load_b32(in, lane + dy, (col + Q * ps) * 4u, 0);
+    const float gl = __builtin_bit_cast(
+        float, __builtin_amdgcn_raw_buffer_load_b32(in, lane + dy, (col + unsigned(l) * ps) * 4u, 0));
+    double rho, th;
+    unpack_ref(ref, rho, th);
+    f[l] = rest_maxwellian(l, rho, th) + double(gl);
+  }
+  if (on_wall_rows(g, y)) wall_site<double>(f, y, g.ly, P.th_bottom, P.th_top, 0.0);
+  float v[Q];
+  const unsigned ref =
+      kF64Collide ? collide_site_local64<kReg>(f, v, P) : collide_site_local<kReg>(f, v, P);
+  const long long own = (long long)(x0 + HX) * g.cs;
+  const __amdgpu_buffer_rsrc_t out = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(dst + own), (short)0, unsigned(min((long long)bx * g.cs, (long long)g.nx * g.cs - own) * 4),
+      kBufferWord3);
+  const unsigned lane_out = (unsigned(x - x0) * cs + Y) * 4u;
+#pragma unroll
+  for (int l = 0; l < Q; ++l)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v[l]), out, lane_out,
+                                          unsigned(l) * ps * 4u, kNonTemporal);
+  __builtin_amdgcn_raw_buffer_store_b32(ref, out, lane_out, Q * ps * 4u, kNonTemporal);
+  const long long site = padded<float>(g, x + HX, y + g.hy);
   if (x < HX) store_local(dst, g, site + (long long)g.lx * g.cs, v, ref);
   if (x >= g.lx - HX) store_local(dst, g, site - (long long)g.lx * g.cs, v, ref);
 }
@@ -795,7 +862,8 @@ unsigned grid_1d(long long n) { return unsigned((n + kThreads - 1) / kThreads); 
 // Calls fn(S{}, A{}) with the storage type S and the arithmetic type A of a
 // precision mode -> (storage type, accumulation type): FP64 storage and
 // collision; shifted FP32 storage with the FP64 collision; shifted FP32
-// storage with FP32 Hermite sums; the local-reference FP32 form (LocalRef).
+// storage with FP32 Hermite sums; the local-reference FP32 form with the
+// FP32 collision (LocalRef) or the FP64 collision (LocalRef64).
 // Moments, equilibrium coefficients and bc are FP64 in every mode.
 template <class Fn>
 hipError_t by_precision(int prec, Fn fn) {
@@ -805,8 +873,10 @@ hipError_t by_precision(int prec, Fn fn) {
     fn(float{}, double{});
   else if (prec == kF32ShiftedF32Sum)
     fn(float{}, float{});
-  else
+  else if (prec == kF32Collide)
     fn(float{}, LocalRef{});
+  else
+    fn(float{}, LocalRef64{});
   return hipGetLastError();
 }
 
@@ -842,12 +912,22 @@ hipError_t launch_fused(const void* src, void* dst, const Geom& g, const Phys& p
     S* b = static_cast<S*>(dst);
     const dim3 grid(t.nb), block(kThreads);
     if constexpr (is_local<A>) {
-      if (regularize)
-        hipLaunchKernelGGL(k_fused_local<true>, grid, block, 0, s, a, b, g, p, t.by, t.bx, t.nty,
-                           t.nb);
-      else
-        hipLaunchKernelGGL(k_fused_local<false>, grid, block, 0, s, a, b, g, p, t.by, t.bx,
+      // column layout: buffer-addressed kernel (its per-tile resources span
+      // a few columns); SoA: planes lie a lattice apart, global addressing
+      constexpr bool k64 = A::f64_collide;
+      const bool column = g.ps < g.cs;
+      if (column && regularize)
+        hipLaunchKernelGGL((k_fused_local_col<true, k64>), grid, block, 0, s, a, b, g, p, t.by,
+                           t.bx, t.nty, t.nb);
+      else if (column)
+        hipLaunchKernelGGL((k_fused_local_col<false, k64>), grid, block, 0, s, a, b, g, p, t.by,
+                           t.bx, t.nty, t.nb);
+      else if (regularize)
+        hipLaunchKernelGGL((k_fused_local<true, k64>), grid, block, 0, s, a, b, g, p, t.by, t.bx,
                            t.nty, t.nb);
+      else
+        hipLaunchKernelGGL((k_fused_local<false, k64>), grid, block, 0, s, a, b, g, p, t.by,
+                           t.bx, t.nty, t.nb);
     } else if (regularize && tape)
       hipLaunchKernelGGL((k_fused<S, A, true, true>), grid, block, 0, s, a, b, g, p, tape, t.by,
                          t.bx, t.nty, t.nb);

@@ -11,7 +11,13 @@
 namespace d2q37 {
 
 // Precision modes (values of lb_lattice.precision): storage / collision.
-enum Precision { kF64 = 0, kF32Shifted = 1, kF32ShiftedF32Sum = 2, kF32Collide = 3 };
+enum Precision {
+  kF64 = 0,
+  kF32Shifted = 1,
+  kF32ShiftedF32Sum = 2,
+  kF32Collide = 3,
+  kF32Local = 4
+};
 
 // Fill `bytes` (multiple of 4) of device memory with zero.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -60,6 +60,9 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int elem_bytes(int prec) { return prec == LB_FP64 ? 8 : 4; }
 
+// FP32 storage relative to the local rest Maxwellian (38 planes)
+bool is_local_form(int prec) { return prec == LB_FP32_COLLIDE || prec == LB_FP32_LOCAL; }
+
 int check_lattice(const lb_lattice* lat) {
   if (!lat) return fail(LB_E_ARG, "lattice is NULL%s");
   if (lat->lx < 6 || lat->ly < 6) return fail(LB_E_ARG, "lx and ly must be >= 6%s");
@@ -69,7 +72,8 @@ int check_lattice(const lb_lattice* lat) {
       (long long)lat->lx * lat->ly > (1LL << 30))
     return fail(LB_E_ARG, "lattice too large (lx <= 2^22, ly <= 2^24, lx*ly <= 2^30)%s");
   if (lat->precision != LB_FP64 && lat->precision != LB_FP32_SHIFTED &&
-      lat->precision != LB_FP32_SHIFTED_F32SUM && lat->precision != LB_FP32_COLLIDE)
+      lat->precision != LB_FP32_SHIFTED_F32SUM && lat->precision != LB_FP32_COLLIDE &&
+      lat->precision != LB_FP32_LOCAL)
     return fail(LB_E_ARG, "unknown precision%s");
   if (lat->ybc != LB_Y_WALLS && lat->ybc != LB_Y_PERIODIC) return fail(LB_E_ARG, "unknown ybc%s");
   if (lat->layout != LB_LAYOUT_SOA && lat->layout != LB_LAYOUT_COLUMN)
@@ -104,7 +108,7 @@ Geom make_geom(const lb_lattice& lat) {
   g.hy = per_line;  // physical row 0 starts 256-byte aligned
   g.ny = int(round_up(size_t(lat.ly) + 2 * size_t(g.hy), size_t(per_line)));
   g.walls = lat.ybc == LB_Y_WALLS;
-  g.np = lat.precision == LB_FP32_COLLIDE ? d2q37::kLocalPlanes : d2q37::Q;
+  g.np = is_local_form(lat.precision) ? d2q37::kLocalPlanes : d2q37::Q;
   if (lat.layout == LB_LAYOUT_SOA) {
     g.ps = (long long)g.nx * g.ny;
     g.cs = g.ny;
@@ -123,7 +127,7 @@ Phys make_phys(const lb_params& par, int prec) {
   p.dtheta = par.tau * (1.0 - par.tau) * (par.gx * par.gx + par.gy * par.gy) / 2.0;
   p.th_bottom = par.t_bottom - 1.0;
   p.th_top = par.t_top - 1.0;
-  p.rho_ref = (prec == LB_FP64 || prec == LB_FP32_COLLIDE) ? 0.0 : par.rho_ref;
+  p.rho_ref = (prec == LB_FP64 || is_local_form(prec)) ? 0.0 : par.rho_ref;
   return p;
 }
 
@@ -131,17 +135,18 @@ size_t buffer_bytes(const Geom& g, int prec) {
   return round_up(size_t(g.np) * size_t(g.nx) * size_t(g.ny) * elem_bytes(prec), kAlign);
 }
 
-// The local-reference form rebuilds a population from the reference of the
+// The local-reference forms rebuild a population from the reference of the
 // site it comes from, which only the fused step has at hand: no split path.
 int check_kernel(int prec, const lb_params& par) {
-  if (prec == LB_FP32_COLLIDE && par.kernel != LB_KERNEL_FUSED)
-    return fail(LB_E_ARG, "LB_FP32_COLLIDE runs the fused kernel only%s");
+  if (is_local_form(prec) && par.kernel != LB_KERNEL_FUSED)
+    return fail(LB_E_ARG, "LB_FP32_COLLIDE and LB_FP32_LOCAL run the fused kernel only%s");
   return LB_OK;
 }
 
 int no_split_stage(lb_ctx* ctx, const char* what) {
-  if (ctx->prec == LB_FP32_COLLIDE)
-    return fail(LB_E_STATE, "%s is not available for LB_FP32_COLLIDE (fused kernel only)", what);
+  if (is_local_form(ctx->prec))
+    return fail(LB_E_STATE, "%s is not available for the local-reference forms (fused only)",
+                what);
   return LB_OK;
 }
 

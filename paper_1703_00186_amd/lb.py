@@ -19,11 +19,13 @@ from . import build as _build
 
 Q = 37
 
-LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM, LB_FP32_COLLIDE = 0, 1, 2, 3
-# precision names: FP64; FP32 storage with the FP64 collision; with FP32
-# Hermite sums (ablation); with the FP32 collision about the rest Maxwellian
+LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM, LB_FP32_COLLIDE, LB_FP32_LOCAL = 0, 1, 2, 3, 4
+# precision names: FP64; shifted FP32 storage with the FP64 collision, or with
+# FP32 Hermite sums (ablation); FP32 storage relative to the local rest
+# Maxwellian with the FP32 collision ("fp32c") or the FP64 collision ("fp32l")
 PRECISIONS = {"fp64": LB_FP64, "fp32s": LB_FP32_SHIFTED, "fp32s_f32sum": LB_FP32_SHIFTED_F32SUM,
-              "fp32c": LB_FP32_COLLIDE}
+              "fp32c": LB_FP32_COLLIDE, "fp32l": LB_FP32_LOCAL}
+LOCAL_FORMS = ("fp32c", "fp32l")
 LB_Y_WALLS, LB_Y_PERIODIC = 0, 1
 LB_LAYOUT_SOA, LB_LAYOUT_COLUMN = 0, 1
 LB_KERNEL_FUSED, LB_KERNEL_SPLIT = 0, 1
@@ -195,8 +197,8 @@ class LB:
     def state_planes(self) -> int:
         """Planes of the compact state: 37 populations, plus the packed
         reference (two FP16 numbers per site) in the local-reference FP32
-        form ("fp32c")."""
-        return Q + 1 if self.precision == "fp32c" else Q
+        forms ("fp32c", "fp32l")."""
+        return Q + 1 if self.precision in LOCAL_FORMS else Q
 
     @property
     def state_shape(self):

@@ -36,7 +36,7 @@ void check_context(int precision, int layout, int kernel, int ybc) {
   lb_lattice lat = {lx, ly, precision, ybc, layout, 0};
   lb_params par = {0.7, 1e-4, -1e-4, 1.5, 0.5, 1.0, 1, kernel, 0, 0};
   size_t need = 0;
-  const bool local = precision == LB_FP32_COLLIDE;
+  const bool local = precision == LB_FP32_COLLIDE || precision == LB_FP32_LOCAL;
   if (local && kernel != LB_KERNEL_FUSED) {  // fused kernel only
     EXPECT(lb_workspace_bytes(&lat, &par, &need) == LB_E_ARG);
     return;
@@ -181,7 +181,8 @@ int main() {
   lb_lattice big = {1 << 16, 1 << 14, LB_FP64, LB_Y_WALLS, LB_LAYOUT_COLUMN, 0};
   EXPECT(lb_workspace_bytes(&big, &par, &need) == LB_OK);
 
-  for (int prec : {LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM, LB_FP32_COLLIDE})
+  for (int prec : {LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM, LB_FP32_COLLIDE,
+                   LB_FP32_LOCAL})
     for (int layout : {LB_LAYOUT_SOA, LB_LAYOUT_COLUMN})
       for (int kernel : {LB_KERNEL_FUSED, LB_KERNEL_SPLIT})
         for (int ybc : {LB_Y_WALLS, LB_Y_PERIODIC}) check_context(prec, layout, kernel, ybc);

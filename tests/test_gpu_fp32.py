@@ -42,33 +42,35 @@ def oparams(**kw):
     return oracle.Params(**p)
 
 
-def test_fp32c_state_encodes_the_equilibrium():
+@pytest.mark.parametrize("precision", ["fp32c", "fp32l"])
+def test_fp32_local_state_encodes_the_equilibrium(precision):
     """The local-reference form of f^eq(rho0, u0, T0): 38 FP32 planes, and the
     populations it decodes to equal the oracle's f^eq to the rounding of the
     deviations from the FP16 reference (far below an FP32 rounding of f)."""
     lx, ly = 40, 70
     rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=1)
-    lb = LB(lx, ly, rho, ux, uy, T, precision="fp32c")
+    lb = LB(lx, ly, rho, ux, uy, T, precision=precision)
     st = host(lb.get_state())
     assert st.shape == (38, lx, ly) and st.dtype == np.float32
     ref = oracle.init_feq(rho, ux, uy, T)
     got = host(lb.populations())
     err = np.abs(got - ref).max() / np.abs(ref).max()
-    print("fp32c init decode error %.2e" % err)
+    print("%s init decode error %.2e" % (precision, err))
     assert err <= 1e-9
     # a state round trip through get_state / set_state is exact
     lb.set_state(torch.from_numpy(st))
     assert np.array_equal(host(lb.get_state()).view(np.uint32), st.view(np.uint32))
 
 
-def test_fp32c_is_fused_only():
+@pytest.mark.parametrize("precision", ["fp32c", "fp32l"])
+def test_fp32_local_is_fused_only(precision):
     from paper_1703_00186_amd.lb import LBError
     lx, ly = 16, 16
     f = workload.rt_fields(lx, ly, seed=1)[:4]
     with pytest.raises(LBError) as e:
-        LB(lx, ly, *f, precision="fp32c", kernel="split")
+        LB(lx, ly, *f, precision=precision, kernel="split")
     assert e.value.code == -1
-    lb = LB(lx, ly, *f, precision="fp32c")
+    lb = LB(lx, ly, *f, precision=precision)
     for stage in (lb.propagate, lb.bc, lb.collide):
         with pytest.raises(LBError) as e:
             stage()
@@ -104,7 +106,7 @@ def test_fp32_state_is_shifted_and_propagate_exact():
 # FP32 sums round relative to the deviation from the rest Maxwellian (at
 # most the size of f, at the interface), and its stored deviations are
 # rounded relative to their own size.
-ONE_STEP_TOL = {"fp32s": 2e-7, "fp32c": 1e-7, "fp32s_f32sum": 1e-6}
+ONE_STEP_TOL = {"fp32s": 2e-7, "fp32c": 1e-7, "fp32l": 1e-7, "fp32s_f32sum": 1e-6}
 
 
 @pytest.mark.parametrize("layout", ["column", "soa"])
@@ -132,36 +134,38 @@ def test_fp32_single_step_close_to_oracle(kernel, precision, layout, regularize)
 @pytest.mark.parametrize("shape", [(64, 80), (7, 65), (130, 257)])
 @pytest.mark.parametrize("layout", ["column", "soa"])
 @pytest.mark.parametrize("regularize", [1, 0])
-def test_fp32c_single_step_close_to_oracle(layout, regularize, shape):
+@pytest.mark.parametrize("precision", ["fp32c", "fp32l"])
+def test_fp32_local_single_step_close_to_oracle(precision, layout, regularize, shape):
     """One fused step of the local-reference form from the state it holds
     after 5 steps (decoded to FP64 populations) against the oracle's step
     from those populations; ragged tiles and the smallest odd sizes too."""
     lx, ly = shape
     rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=2)
     P = oparams(regularize=regularize)
-    lb = LB(lx, ly, rho, ux, uy, T, precision="fp32c", layout=layout, regularize=regularize)
+    lb = LB(lx, ly, rho, ux, uy, T, precision=precision, layout=layout, regularize=regularize)
     lb.step(5)
     f = host(lb.populations())
     lb.step(1)
     ref = oracle.run(f, P, 1)
     got = host(lb.populations())
     err = np.abs(got - ref).max() / np.abs(ref).max()
-    print("fp32c %dx%d %s reg=%d one step: %.2e" % (lx, ly, layout, regularize, err))
-    assert err <= ONE_STEP_TOL["fp32c"]
+    print("%s %dx%d %s reg=%d one step: %.2e" % (precision, lx, ly, layout, regularize, err))
+    assert err <= ONE_STEP_TOL[precision]
 
 
-def test_fp32c_periodic_y_single_step():
+@pytest.mark.parametrize("precision", ["fp32c", "fp32l"])
+def test_fp32_local_periodic_y_single_step(precision):
     lx, ly = 40, 70
     rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=3)
     P = oparams(ybc=1)
-    lb = LB(lx, ly, rho, ux, uy, T, precision="fp32c", ybc="periodic")
+    lb = LB(lx, ly, rho, ux, uy, T, precision=precision, ybc="periodic")
     lb.step(3)
     f = host(lb.populations())
     lb.step(1)
     ref = oracle.run(f, P, 1)
     err = np.abs(host(lb.populations()) - ref).max() / np.abs(ref).max()
-    print("fp32c periodic y one step: %.2e" % err)
-    assert err <= ONE_STEP_TOL["fp32c"]
+    print("%s periodic y one step: %.2e" % (precision, err))
+    assert err <= ONE_STEP_TOL[precision]
 
 
 @pytest.mark.parametrize("rho_ref", [0.0, 1.3])
@@ -194,10 +198,10 @@ def oracle_256_2000():
 
 # per-field bounds after 2000 steps: the 1e-5 target for fp32c (measured
 # ~1e-7); the shifted storage's measured rounding floor for fp32s
-BOUND_256 = {"fp32c": 1e-5, "fp32s": 1e-5}
+BOUND_256 = {"fp32c": 1e-5, "fp32l": 1e-5, "fp32s": 1e-5}
 
 
-@pytest.mark.parametrize("precision", ["fp32c", "fp32s"])
+@pytest.mark.parametrize("precision", ["fp32c", "fp32l", "fp32s"])
 def test_fp32_vs_oracle_256_2000_steps(precision, oracle_256_2000):
     fields, ref = oracle_256_2000
     lb = LB(256, 256, *fields, precision=precision)
@@ -235,6 +239,7 @@ def test_fp32_shift_density_vs_oracle_256_200_steps(precision, rho_ref):
 # fp32c: the 1e-5 target; fp32s: its measured rounding floor in u (max|du|
 # about 4.6e-8 against max|u| = 3.2e-3 after 2000 steps), rho and T 1e-5
 BOUND_4096 = {"fp32c": {"rho": 1e-5, "u": 1e-5, "T": 1e-5},
+              "fp32l": {"rho": 1e-5, "u": 1e-5, "T": 1e-5},
               "fp32s": {"rho": 1e-5, "u": 5e-5, "T": 1e-5}}
 
 
@@ -247,7 +252,7 @@ def test_fp32_vs_fp64_gpu_4096_2000_steps():
     del lb64
     torch.cuda.empty_cache()
     results = {}
-    for precision in ("fp32c", "fp32s"):
+    for precision in ("fp32c", "fp32l", "fp32s"):
         lb32 = LB(lx, ly, *f, precision=precision)
         lb32.step(steps)
         results[precision] = field_errors([host(t) for t in lb32.moments()], m64)

@@ -48,6 +48,7 @@ def oparams():
     (8192, 4096, "fp64", "multimode", 10),
     (8192, 4096, "fp32s", "multimode", 10),
     (8192, 4096, "fp32c", "multimode", 10),
+    (8192, 4096, "fp32l", "multimode", 10),
 ])
 def test_one_step_at_sampled_sites(lx, ly, precision, mode, warm):
     seed = workload.config_seed({2048: 2, 4096: 3 if lx == 4096 else 5}[ly])
@@ -65,7 +66,7 @@ def test_one_step_at_sampled_sites(lx, ly, precision, mode, warm):
     # rounding of each stored population (2^-24) plus the input's own
     # rounding; the FP32 collision adds its FP32 sums of the deviation from
     # the rest Maxwellian (a few 1e-7 of the largest population)
-    tol = {"fp64": 1e-13, "fp32s": 3e-7, "fp32c": 1e-7}[precision]
+    tol = {"fp64": 1e-13, "fp32s": 3e-7, "fp32c": 1e-7, "fp32l": 1e-7}[precision]
     err = np.abs(got - ref).max() / np.abs(ref).max()
     print("%s %dx%d one step at %d sampled sites: %.2e" % (precision, lx, ly, len(xs), err))
     assert err <= tol

@@ -31,7 +31,7 @@ def reference(f, t_bottom, t_top):
 
 
 @pytest.mark.parametrize("layout", ["column", "soa"])
-@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp32c"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp32c", "fp32l"])
 @pytest.mark.parametrize("shape", [(96, 200), (70, 33), (256, 128)])
 def test_observables_match_oracle_moments(precision, shape, layout):
     lx, ly = shape

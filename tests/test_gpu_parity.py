@@ -239,7 +239,7 @@ def bits(t):
     return t.view(torch.int64 if t.dtype == torch.float64 else torch.int32)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp32c"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp32c", "fp32l"])
 def test_checkpoint_file_round_trip(tmp_path, precision):
     """save_checkpoint / load_checkpoint: the resumed run is bit-identical."""
     lb, fields = make(48, 40, precision=precision)

@@ -40,7 +40,7 @@ def mode_amplitude(lb, comp, k):
     return 2 * np.mean(u * np.sin(k * np.arange(lb.lx)))
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-3), ("fp32s", 5e-3), ("fp32c", 1e-3)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-3), ("fp32s", 5e-3), ("fp32c", 1e-3), ("fp32l", 1e-3)])
 @pytest.mark.parametrize("lx,T", [(256, 1.0), (512, 0.6)])
 def test_shear_wave_viscosity(r, lx, T, precision, tol):
     ly, tau, U0 = 8, 0.7, 1e-3
