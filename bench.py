@@ -219,16 +219,15 @@ def time_split_kernels(lb, steps: int, torch) -> dict:
 
 # FP32 forms timed beside the FP64 headline: (key, precision, what it is)
 FP32_FORMS = (
-    ("fp32_shifted", "fp32c",
-     "FP32 storage of each population's deviation from its writer site's rest Maxwellian "
-     "(+ that site's FP16 density and temperature), FP32 collision (FP64 for the collision "
-     "invariants, the equilibrium coefficients and a conservation correction)"),
-    ("fp32_local_fp64_collide", "fp32l",
-     "FP32 storage of each population's deviation from its writer site's rest Maxwellian "
-     "(+ that site's FP16 density and temperature), FP64 collision"),
-    ("fp32_storage_fp64_collide", "fp32s", "FP32 storage of f - w rho_ref, FP64 collision"),
+    ("fp32_local", "fp32l",
+     "FP32 storage of each population's deviation from the rest Maxwellian of the site that "
+     "collided it (+ that site's FP16 density and temperature), FP64 collision"),
+    ("fp32_local_fp32_collide", "fp32c",
+     "the same storage with an FP32 collision (FP32 Hermite sums of the deviation; FP64 for "
+     "the collision invariants, the equilibrium coefficients and a conservation correction)"),
+    ("fp32_shifted", "fp32s", "FP32 storage of f - w rho_ref (rho_ref = 1), FP64 collision"),
     ("fp32_shifted_f32sum", "fp32s_f32sum",
-     "ablation: FP32 storage, the FP64 collision's Hermite sums in FP32"),
+     "ablation: FP32 storage of f - w rho_ref, the FP64 collision's Hermite sums in FP32"),
 )
 FP32_WARMUP, FP32_TIMED, FP32_ERROR_STEPS = 20, 200, 2000
 

@@ -179,13 +179,19 @@ __global__ __launch_bounds__(kThreads) void k_fused_local(const float* __restric
   int x, y;
   if (!site_of(g, by, bx, nty, nb, x, y)) return;
   const long long site = padded<float>(g, x + HX, y + g.hy);
+  float gv[Q];
+  unsigned rv[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) gv[l] = src[l * g.ps + site - EX[l] * g.cs - EY[l]];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) rv[l] = ref_at(src, g, site - EX[l] * g.cs - EY[l]);
+  __builtin_amdgcn_sched_barrier(0);
   double f[Q];
 #pragma unroll
   for (int l = 0; l < Q; ++l) {
-    const long long s = site - EX[l] * g.cs - EY[l];
     double rho, th;
-    unpack_ref(ref_at(src, g, s), rho, th);
-    f[l] = rest_maxwellian(l, rho, th) + double(src[l * g.ps + s]);
+    unpack_ref(rv[l], rho, th);
+    f[l] = rest_maxwellian(l, rho, th) + double(gv[l]);
   }
   if (on_wall_rows(g, y)) wall_site<double>(f, y, g.ly, P.th_bottom, P.th_top, 0.0);
   float v[Q];
@@ -225,17 +231,24 @@ __global__ __launch_bounds__(kThreads) void k_fused_local_col(const float* __res
       __builtin_amdgcn_make_buffer_rsrc((void*)(src + first), (short)0, span, kBufferWord3);
   const unsigned Y = unsigned(y + g.hy);
   const unsigned lane = (unsigned(x - x0) * cs + Y - 3u) * 4u;
+  // all 74 loads first (the scheduling barrier keeps the decode from being
+  // interleaved with them, which would cap the loads in flight)
+  unsigned gv[Q], rv[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l)
+    gv[l] = __builtin_amdgcn_raw_buffer_load_b32(
+        in, lane + unsigned(3 - EY[l]) * 4u, (unsigned(HX - EX[l]) * cs + unsigned(l) * ps) * 4u, 0);
+#pragma unroll
+  for (int l = 0; l < Q; ++l)
+    rv[l] = __builtin_amdgcn_raw_buffer_load_b32(
+        in, lane + unsigned(3 - EY[l]) * 4u, (unsigned(HX - EX[l]) * cs + Q * ps) * 4u, 0);
+  __builtin_amdgcn_sched_barrier(0);
   double f[Q];
 #pragma unroll
   for (int l = 0; l < Q; ++l) {
-    const unsigned col = unsigned(HX - EX[l]) * cs;  // source column, relative
-    const unsigned dy = unsigned(3 - EY[l]) * 4u;
-    const unsigned ref = __builtin_amdgcn_raw_buffer_load_b32(in, lane + dy, (col + Q * ps) * 4u, 0);
-    const float gl = __builtin_bit_cast(
-        float, __builtin_amdgcn_raw_buffer_load_b32(in, lane + dy, (col + unsigned(l) * ps) * 4u, 0));
     double rho, th;
-    unpack_ref(ref, rho, th);
-    f[l] = rest_maxwellian(l, rho, th) + double(gl);
+    unpack_ref(rv[l], rho, th);
+    f[l] = rest_maxwellian(l, rho, th) + double(__builtin_bit_cast(float, gv[l]));
   }
   if (on_wall_rows(g, y)) wall_site<double>(f, y, g.ly, P.th_bottom, P.th_top, 0.0);
   float v[Q];

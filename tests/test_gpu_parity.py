@@ -196,6 +196,51 @@ def test_check_finite_reports_nonfinite_state():
     assert ei.value.code == -5
 
 
+def _uniform_state(lb, f37):
+    """The state tensor of a lattice whose every site holds the populations
+    f37 (FP64 [37]), in the context's storage form: f itself (FP64),
+    f - w rho_ref (shifted FP32), or deviations from a zero reference (the
+    local-reference forms: packed reference word 0 means M = 0)."""
+    _, _, w, _ = oracle.model()
+    f = np.broadcast_to(np.asarray(f37)[:, None, None], (37, lb.lx, lb.ly))
+    if lb.precision == "fp64":
+        return torch.from_numpy(np.ascontiguousarray(f))
+    if lb.precision in ("fp32s", "fp32s_f32sum"):
+        return torch.from_numpy((f - 1.0 * w[:, None, None]).astype(np.float32))
+    st = np.zeros((38, lb.lx, lb.ly), np.float32)
+    st[:37] = f
+    return torch.from_numpy(st)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp32c", "fp32l"])
+@pytest.mark.parametrize("case", ["rho", "T"])
+def test_check_finite_reports_unphysical_finite_state(precision, case):
+    """check_finite's rho <= 0 and T <= 0 branches: a uniform, finite state
+    with negative density (f = -w), or with positive density and negative
+    temperature (rest population 1, the four nearest -0.01 each), is its own
+    collision fixed point on a periodic lattice without gravity; the scan
+    after one step must report it while every population is finite."""
+    cx, cy, w, _ = oracle.model()
+    if case == "rho":
+        f37 = -w
+    else:
+        f37 = np.where(np.abs(cx) + np.abs(cy) == 1, -0.01, 0.0)
+        f37[18] = 1.0
+    lx, ly = 24, 20
+    lb, _ = make(lx, ly, precision=precision, ybc="periodic", g=(0.0, 0.0), check_finite=1)
+    lb.set_state(_uniform_state(lb, f37))
+    with pytest.raises(lbmod.LBError) as ei:
+        lb.step(1)
+    assert ei.value.code == -5
+    pops = host(lb.populations())
+    assert np.isfinite(pops).all()
+    rho, _, _, T = [host(t) for t in lb.moments()]
+    if case == "rho":
+        assert (rho <= 0).all()
+    else:
+        assert (rho > 0).all() and (T <= 0).all()
+
+
 def test_resume_from_checkpoint_is_bit_identical():
     lx, ly = 64, 64
     lb, _ = make(lx, ly)

@@ -78,3 +78,23 @@ def test_bc_emits_scaled_wall_maxwellian(model):
             rho_w = out[U, x, y] / v[U]
             assert np.allclose(rho_w, rho_w[0], rtol=1e-14)
             assert abs(ft[K, x, y].sum() - rho_w[0] * v[K].sum()) < 1e-13
+
+
+def test_wall_maxwellians_and_bc_denominators(model):
+    """Consequences of the units reading (velocities c_l = r e_l, T = 1 the
+    quadrature's temperature) for the walls of the workloads (T_bottom 1.5,
+    T_top 0.5): the cold wall's Maxwellian f^eq(1, 0, 0.5) has 12 negative
+    entries (min v/w = -0.228: the 4th-order expansion far from T = 1), yet
+    the denominators sum_K v of the bc, over the populations known at each
+    wall row, stay at 0.70 or more; a change of units or wall temperatures
+    that brought one near zero would make rho_w ill-conditioned."""
+    cx, cy, w, _ = model
+    ly = 12
+    for T_wall, neg in ((1.5, 0), (0.5, 12)):
+        v = oracle.equilibrium(1.0, 0.0, 0.0, T_wall)
+        assert int((v < 0).sum()) == neg
+        for y in (0, 1, 2, ly - 3, ly - 2, ly - 1):
+            known = (y - cy >= 0) & (y - cy < ly)
+            assert v[known].sum() >= 0.5, (T_wall, y, v[known].sum())
+    v = oracle.equilibrium(1.0, 0.0, 0.0, 0.5)
+    assert abs((v / w).min() - (-0.228)) < 1e-3
