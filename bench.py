@@ -739,6 +739,31 @@ def run_ablations(args, torch) -> list:
     return out
 
 
+def run_forms(args, torch) -> list:
+    """Only the fused step of each named storage form on the headline lattice:
+    --warmup untimed steps, then --steps timed ones (HIP events on the
+    kernels' stream); one record per form.  For counter and trace profiles."""
+    from paper_1703_00186_amd import workload
+    from paper_1703_00186_amd.lb import LB
+
+    lx, ly = args.lx, args.ly
+    fields = workload.rt_fields(lx, ly, seed=workload.config_seed(2))[:4]
+    out = []
+    for prec in args.forms:
+        lb = LB(lx, ly, *fields, precision=prec, layout=args.layout)
+        lb.step(args.warmup)
+        t = time_steps(lb, args.steps, torch)
+        gbs = bytes_per_site(prec) * lx * ly / (t / args.steps) / 1e9
+        out.append({"form": prec, "lattice": [lx, ly], "steps": args.steps,
+                    "ms_per_step": round(t / args.steps * 1e3, 5),
+                    "MLUPS": round(mlups(lx * ly * args.steps, t), 1), "GB/s": round(gbs, 1),
+                    "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        log("forms: %s" % out[-1])
+        del lb
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_optimised(lx: int, ly: int, fields, steps: int = 40) -> dict:
     """The vectorised multicore CPU implementation of the same step (a
     stronger CPU comparison than the oracle), on this host's cores."""
@@ -789,6 +814,10 @@ def main(argv=None) -> int:
                     help="steps of the 4096 x 4096 FP32-precision workload")
     ap.add_argument("--production-steps", type=int, default=5000,
                     help="steps of the 8192 x 4096 production workload")
+    ap.add_argument("--forms", nargs="+", default=None,
+                    choices=["fp64", "fp32l", "fp32c", "fp32s", "fp32s_f32sum"],
+                    help="time only the fused step of these storage forms on the headline "
+                         "lattice (one JSON record each; for profiles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scale reference)")
     args = ap.parse_args(argv)
@@ -806,6 +835,12 @@ def main(argv=None) -> int:
 
     if args.rt_run:
         print(json.dumps(run_rt(args, torch)), flush=True)
+        return 0
+    if args.forms:
+        for rec in run_forms(args, torch):
+            print(json.dumps(rec), flush=True)
+        if args.copy_calibration:
+            copy_calibration(torch)
         return 0
     if args.workloads is not None or args.ablations:
         for rec in (run_workloads if args.workloads is not None else run_ablations)(args, torch):
