@@ -43,8 +43,8 @@ def mlups(sites: int, seconds: float) -> float:
 
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_SUMMARY = os.path.join(PROFILES, "k_fused_fp64_rt1920x2048_hbm_traffic.md")
-VALU_SUMMARY = os.path.join(PROFILES, "k_fused_fp64_rt1920x2048_valu.md")
-FP32_VALU_SUMMARY = os.path.join(PROFILES, "k_fused_fp32_rt4096x4096_valu.md")
+VALU_SUMMARY = os.path.join(PROFILES, "k_fused_forms_rt1920x2048_valu.md")
+FP32_VALU_SUMMARY = VALU_SUMMARY
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 KERNEL_SOURCES = ["paper_1703_00186_amd/csrc/d2q37_kernels.hip",
@@ -262,6 +262,10 @@ def fp32_legs(lx: int, ly: int, fields, layout: str, fp64_mlups: float, torch) -
             "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "error_vs_fp64_gpu": {k: float("%.3g" % v) for k, v in errs.items()},
             "error_after_steps": FP32_ERROR_STEPS}
+        vals = summary_values(TRAFFIC_SUMMARY)
+        if vals.get("lattice") == "%dx%d" % (lx, ly) and (prec + "_hbm_bytes_per_launch") in vals:
+            out[key]["traffic"] = float(vals[prec + "_hbm_bytes_per_launch"])
+            out[key]["traffic_unit"] = "bytes per launch"
         fl = counted_fp32_mode_flops(prec)
         if fl is not None:
             rate = sites / (t32 / FP32_TIMED) / 1e12
