@@ -257,6 +257,19 @@ int lb_adjoint_step(lb_ctx* ctx, const double* tape_j, const double* lambda_in,
 int lb_adjoint_workspace_bytes(lb_ctx* ctx, size_t* bytes);
 int lb_adjoint_run(lb_ctx* ctx, int n, const double* tape, double* lambda, void* workspace,
                    size_t workspace_bytes);
+/* lb_adjoint_run_static: lb_adjoint_run without a workspace argument, for
+ * callers that cannot allocate device memory (code under graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  The two padded adjoint
+ * buffers live in a 64 MiB array the library holds on each GPU it runs on
+ * (for the life of the process); the first call on a device looks its address
+ * up.  The call allocates nothing; its result is that of lb_adjoint_run, bit
+ * for bit.  Lattices whose two padded FP64 buffers exceed 64 MiB
+ * (2 * 37 * (lx + 6) * (ly + 64, rounded up to 32) * 8 bytes; about 110,000
+ * sites) are rejected with LB_E_WORKSPACE.  All calls on one GPU share that
+ * array: calls that overlap on one GPU (other streams, other threads, other
+ * contexts) race and must be serialised by the caller.  Errors as
+ * lb_adjoint_run, plus LB_E_HIP when the array's address cannot be looked up. */
+int lb_adjoint_run_static(lb_ctx* ctx, int n, const double* tape, double* lambda);
 int lb_init_adjoint(lb_ctx* ctx, const double* rho0, const double* ux0,
                     const double* uy0, const double* T0, const double* lambda0,
                     double* drho0, double* dux0, double* duy0, double* dT0);

@@ -96,4 +96,10 @@ hipError_t launch_init_adjoint(const double* lam0, const double* rho, const doub
                                const double* uy, const double* T, double* drho, double* dux,
                                double* duy, double* dT, const Geom& g, hipStream_t s);
 
+// The library's per-GPU static scratch (lb_adjoint_run_static): its size,
+// and its device address on the current device (looked up on the first call
+// for each device, then kept).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;  // 64 MiB
+hipError_t static_scratch(void** out);
+
 }  // namespace d2q37

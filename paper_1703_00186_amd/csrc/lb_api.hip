@@ -48,6 +48,13 @@ int hip_fail(hipError_t e, const char* where) {
   return LB_E_HIP;
 }
 
+// The static scratch of lb_adjoint_run_static (csrc/lb_scratch.hip).
+int scratch_address(void** out) {
+  const hipError_t e = d2q37::static_scratch(out);
+  if (e != hipSuccess) return hip_fail(e, "lb_adjoint_run_static: scratch address");
+  return LB_OK;
+}
+
 #define LB_HIP(call, where)                   \
   do {                                        \
     hipError_t e_ = (call);                   \
@@ -219,6 +226,54 @@ int one_step(lb_ctx* c, double* tape) {
     c->steps_since_check = 0;
     return check_finite_now(c);
   }
+  return LB_OK;
+}
+
+// n transposed steps, lambda^n -> lambda^0 in place, with the two padded FP64
+// buffers at ws (2 * buffer_bytes(g, LB_FP64) bytes, 256-byte aligned).
+int adjoint_run(lb_ctx* ctx, int n, const double* tape, double* lambda, char* ws) {
+  const size_t nb = buffer_bytes(ctx->g, LB_FP64);
+  double* m0 = reinterpret_cast<double*>(ws);
+  double* m1 = reinterpret_cast<double*>(ws + nb);
+  const Geom& g = ctx->g;
+  const bool walls = g.walls != 0;
+  const long long per = 4LL * g.lx * g.ly;
+  const int reg = ctx->par.regularize;
+  // Where the two compact lambda arrays fit in the 256 MB Infinity Cache the
+  // scatter form's partial-sector stores cost nothing and it is the faster
+  // one (measured 25 vs 33 us at 512 x 512; the gather form wins from
+  // 768 x 768 up and on lattices too small to fill the GPU); same result.
+  const long long sites = (long long)g.lx * g.ly;
+  const bool scatter = sites >= (1LL << 17) && 2 * 37 * 8 * sites <= (256LL << 20);
+  if (scatter) {
+    double* in = lambda;
+    double* out = m0;  // a compact array fits in one padded buffer
+    for (int j = n - 1; j >= 0; --j) {
+      LB_HIP(d2q37::launch_adjoint_step(tape + per * j, in, out, g, ctx->p, reg, ctx->stream),
+             "adjoint_run step");
+      std::swap(in, out);
+    }
+    if (in != lambda)
+      LB_HIP(hipMemcpyAsync(lambda, in, size_t(37) * size_t(sites) * sizeof(double),
+                            hipMemcpyDeviceToDevice, ctx->stream),
+             "adjoint_run copy");
+    return LB_OK;
+  }
+  if (walls) {  // the gather reads zero beyond the walls
+    LB_HIP(d2q37::launch_zero_pad_rows(m0, g, LB_FP64, ctx->stream), "adjoint_run pad rows");
+    LB_HIP(d2q37::launch_zero_pad_rows(m1, g, LB_FP64, ctx->stream), "adjoint_run pad rows");
+  }
+  LB_HIP(d2q37::launch_adjoint_mu(tape + per * (n - 1), lambda, true, m0, g, ctx->p, reg,
+                                  ctx->stream),
+         "adjoint_run first step");
+  for (int j = n - 2; j >= 0; --j) {
+    if (!walls) LB_HIP(d2q37::launch_halo(m0, g, LB_FP64, ctx->stream), "adjoint_run halo");
+    LB_HIP(d2q37::launch_adjoint_mu(tape + per * j, m0, false, m1, g, ctx->p, reg, ctx->stream),
+           "adjoint_run step");
+    std::swap(m0, m1);
+  }
+  if (!walls) LB_HIP(d2q37::launch_halo(m0, g, LB_FP64, ctx->stream), "adjoint_run halo");
+  LB_HIP(d2q37::launch_adjoint_gather(m0, lambda, g, ctx->stream), "adjoint_run gather");
   return LB_OK;
 }
 
@@ -515,48 +570,25 @@ int lb_adjoint_run(lb_ctx* ctx, int n, const double* tape, double* lambda, void*
     return fail(LB_E_WORKSPACE, "adjoint workspace must be 256-byte aligned%s");
   const size_t nb = buffer_bytes(ctx->g, LB_FP64);
   if (workspace_bytes < 2 * nb) return fail(LB_E_WORKSPACE, "adjoint workspace too small%s");
-  double* m0 = static_cast<double*>(workspace);
-  double* m1 = reinterpret_cast<double*>(static_cast<char*>(workspace) + nb);
-  const Geom& g = ctx->g;
-  const bool walls = g.walls != 0;
-  const long long per = 4LL * g.lx * g.ly;
-  const int reg = ctx->par.regularize;
-  // Where the two compact lambda arrays fit in the 256 MB Infinity Cache the
-  // scatter form's partial-sector stores cost nothing and it is the faster
-  // one (measured 25 vs 33 us at 512 x 512; the gather form wins from
-  // 768 x 768 up and on lattices too small to fill the GPU); same result.
-  const long long sites = (long long)g.lx * g.ly;
-  const bool scatter = sites >= (1LL << 17) && 2 * 37 * 8 * sites <= (256LL << 20);
-  if (scatter) {
-    double* in = lambda;
-    double* out = m0;  // a compact array fits in one padded buffer
-    for (int j = n - 1; j >= 0; --j) {
-      LB_HIP(d2q37::launch_adjoint_step(tape + per * j, in, out, g, ctx->p, reg, ctx->stream),
-             "adjoint_run step");
-      std::swap(in, out);
-    }
-    if (in != lambda)
-      LB_HIP(hipMemcpyAsync(lambda, in, size_t(37) * size_t(sites) * sizeof(double),
-                            hipMemcpyDeviceToDevice, ctx->stream),
-             "adjoint_run copy");
-    return LB_OK;
-  }
-  if (walls) {  // the gather reads zero beyond the walls
-    LB_HIP(d2q37::launch_zero_pad_rows(m0, g, LB_FP64, ctx->stream), "adjoint_run pad rows");
-    LB_HIP(d2q37::launch_zero_pad_rows(m1, g, LB_FP64, ctx->stream), "adjoint_run pad rows");
-  }
-  LB_HIP(d2q37::launch_adjoint_mu(tape + per * (n - 1), lambda, true, m0, g, ctx->p, reg,
-                                  ctx->stream),
-         "adjoint_run first step");
-  for (int j = n - 2; j >= 0; --j) {
-    if (!walls) LB_HIP(d2q37::launch_halo(m0, g, LB_FP64, ctx->stream), "adjoint_run halo");
-    LB_HIP(d2q37::launch_adjoint_mu(tape + per * j, m0, false, m1, g, ctx->p, reg, ctx->stream),
-           "adjoint_run step");
-    std::swap(m0, m1);
-  }
-  if (!walls) LB_HIP(d2q37::launch_halo(m0, g, LB_FP64, ctx->stream), "adjoint_run halo");
-  LB_HIP(d2q37::launch_adjoint_gather(m0, lambda, g, ctx->stream), "adjoint_run gather");
-  return LB_OK;
+  return adjoint_run(ctx, n, tape, lambda, static_cast<char*>(workspace));
+}
+
+int lb_adjoint_run_static(lb_ctx* ctx, int n, const double* tape, double* lambda) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  rc = need_fp64(ctx, "lb_adjoint_run_static");
+  if (rc) return rc;
+  if (n < 0) return fail(LB_E_ARG, "n must be >= 0%s");
+  if (2 * buffer_bytes(ctx->g, LB_FP64) > d2q37::kStaticScratchBytes)
+    return fail(LB_E_WORKSPACE,
+                "lattice too large for the 64 MiB static adjoint scratch "
+                "(2 padded FP64 buffers; use lb_adjoint_run with a workspace)%s");
+  if (n == 0) return LB_OK;
+  if (!tape || !lambda) return fail(LB_E_ARG, "NULL argument%s");
+  void* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc) return rc;
+  return adjoint_run(ctx, n, tape, lambda, static_cast<char*>(ws));
 }
 
 int lb_init_adjoint(lb_ctx* ctx, const double* rho0, const double* ux0, const double* uy0,

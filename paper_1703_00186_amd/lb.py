@@ -38,7 +38,8 @@ EXPORTS = [
     "lb_set_params", "lb_step", "lb_moments", "lb_get_state", "lb_set_state",
     "lb_get_populations", "lb_halo", "lb_propagate", "lb_bc", "lb_collide", "lb_get_scratch",
     "lb_set_scratch", "lb_observables", "lb_run_observed", "lb_step_record", "lb_loss_ke",
-    "lb_adjoint_step", "lb_adjoint_workspace_bytes", "lb_adjoint_run", "lb_init_adjoint",
+    "lb_adjoint_step", "lb_adjoint_workspace_bytes", "lb_adjoint_run", "lb_adjoint_run_static",
+    "lb_init_adjoint",
 ]
 
 N_PROFILES = 6  # rho, u_x, u_y, T, rho |u|^2 / 2, rho T (row averages)
@@ -108,6 +109,7 @@ def load_library():
         "lb_adjoint_step": ([vp, vp, vp, vp], i),
         "lb_adjoint_workspace_bytes": ([vp, ctypes.POINTER(sz)], i),
         "lb_adjoint_run": ([vp, i, vp, vp, vp, sz], i),
+        "lb_adjoint_run_static": ([vp, i, vp, vp], i),
         "lb_init_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], i),
     }
     for name, (args, res) in sig.items():
@@ -439,6 +441,20 @@ class LB:
             self._adj_ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         _check(self.lib.lb_adjoint_run(self.ctx, n, _ptr(tape), _ptr(lam), _ptr(self._adj_ws),
                                        self._adj_ws.numel()))
+        return lam
+
+    def adjoint_run_static(self, tape: torch.Tensor, lam: torch.Tensor, n: int = None):
+        """As adjoint_run, through lb_adjoint_run_static: no workspace, the
+        library's per-GPU 64 MiB scratch (small lattices only; calls that
+        overlap on one GPU race)."""
+        n = tape.shape[0] if n is None else int(n)
+        if (not isinstance(tape, torch.Tensor) or tape.dim() != 4 or tape.shape[0] < n
+                or tuple(tape.shape[1:]) != (4, self.lx, self.ly)):
+            raise ValueError("tape must be [>=n, 4, lx, ly]")
+        self._expect(tape, tape.shape, torch.float64, "tape")
+        self._check_lambda(lam)
+        self._sync_stream()
+        _check(self.lib.lb_adjoint_run_static(self.ctx, n, _ptr(tape), _ptr(lam)))
         return lam
 
     def init_adjoint(self, rho0, ux0, uy0, T0, lam0: torch.Tensor):

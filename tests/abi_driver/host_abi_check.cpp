@@ -122,6 +122,9 @@ void check_context(int precision, int layout, int kernel, int ybc) {
     EXPECT(lb_adjoint_run(ctx, 3, t, la, aws, adj - 1) == LB_E_WORKSPACE);
     EXPECT(lb_adjoint_run(ctx, 3, t, la, static_cast<char*>(aws) + 8, adj) == LB_E_WORKSPACE);
     EXPECT(lb_adjoint_run(ctx, 3, nullptr, la, aws, adj) == LB_E_ARG);
+    EXPECT(lb_adjoint_run_static(ctx, -1, t, la) == LB_E_ARG);
+    EXPECT(lb_adjoint_run_static(ctx, 0, nullptr, nullptr) == LB_OK);
+    EXPECT(lb_adjoint_run_static(ctx, 3, nullptr, la) == LB_E_ARG);
     std::free(aws);
     EXPECT(lb_init_adjoint(ctx, f, f + S, f + 2 * S, f + 3 * S, lbuf, out.data(), nullptr,
                            nullptr, out.data() + 3 * S) == LB_OK);
@@ -134,6 +137,7 @@ void check_context(int precision, int layout, int kernel, int ybc) {
     size_t adj = 0;
     EXPECT(lb_adjoint_workspace_bytes(ctx, &adj) == LB_E_STATE);
     EXPECT(lb_adjoint_run(ctx, 2, t, la, nullptr, 0) == LB_E_STATE);
+    EXPECT(lb_adjoint_run_static(ctx, 2, t, la) == LB_E_STATE);
     EXPECT(lb_init_adjoint(ctx, f, f + S, f + 2 * S, f + 3 * S, la, nullptr, nullptr, nullptr,
                            nullptr) == LB_E_STATE);
   }
@@ -180,6 +184,24 @@ int main() {
   EXPECT(lb_workspace_bytes(&lat, &bad, &need) == LB_E_ARG);
   lb_lattice big = {1 << 16, 1 << 14, LB_FP64, LB_Y_WALLS, LB_LAYOUT_COLUMN, 0};
   EXPECT(lb_workspace_bytes(&big, &par, &need) == LB_OK);
+
+  {  // lb_adjoint_run_static rejects lattices beyond its 64 MiB scratch before any launch
+    lb_lattice bl = {400, 300, LB_FP64, LB_Y_WALLS, LB_LAYOUT_COLUMN, 0};
+    lb_params bp = {0.7, 0.0, -1e-4, 1.5, 0.5, 1.0, 1, LB_KERNEL_FUSED, 0, 0};
+    size_t bneed = 0;
+    EXPECT(lb_workspace_bytes(&bl, &bp, &bneed) == LB_OK);
+    void* bws = std::aligned_alloc(256, round256(bneed));
+    const size_t BS = size_t(400) * 300;
+    std::vector<double> bf(4 * BS, 1.0), blam(37 * BS), btape(4 * BS);
+    lb_ctx* bctx = nullptr;
+    EXPECT(lb_init(&bl, &bp, bws, round256(bneed), nullptr, bf.data(), bf.data() + BS,
+                   bf.data() + 2 * BS, bf.data() + 3 * BS, &bctx) == LB_OK);
+    EXPECT(lb_adjoint_run_static(bctx, 1, btape.data(), blam.data()) == LB_E_WORKSPACE);
+    EXPECT(std::string(lb_last_error()).find("64 MiB") != std::string::npos);
+    EXPECT(lb_adjoint_run_static(nullptr, 1, btape.data(), blam.data()) == LB_E_ARG);
+    lb_free(bctx);
+    std::free(bws);
+  }
 
   for (int prec : {LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM, LB_FP32_COLLIDE,
                    LB_FP32_LOCAL})

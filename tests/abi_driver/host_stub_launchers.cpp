@@ -63,4 +63,7 @@ hipError_t launch_init_adjoint(const double*, const double*, const double*, cons
   return hipSuccess;
 }
 
+// No device memory on the host-only build: the static scratch is unavailable.
+hipError_t static_scratch(void**) { return hipErrorNoDevice; }
+
 }  // namespace d2q37
