@@ -250,10 +250,21 @@ def test_gradient_512_vs_finite_differences_and_cost():
     ke_fwd = float(host(lb.loss_ke(with_lambda=False)[0])[0])
     t_fwd = time.perf_counter() - t0
     assert abs(ke_fwd - ke) <= 1e-14 * ke
-    # Central differences carry rounding noise ~ u / h, with u the absolute
-    # rounding noise of KE after the run (a few ulps of KE); at h = 1e-6 that
-    # alone is ~1e-6 of |dKE/da| here.  h = 1e-6 is checked against that
-    # floor, h = 1e-5 (noise and truncation both ~1e-7) against 1e-6.
+    # Central differences carry the rounding noise of KE divided by h.  That
+    # noise is measured: KE at nine points of a line a0 + t d (d a seeded
+    # unit vector, |t| <= 4e-9) minus its least-squares quadratic leaves the
+    # rounding alone (the cubic term is ~1e-25 of KE); its rms sigma gives a
+    # central difference an error of sigma / (sqrt(2) h) per component.
+    # h = 1e-6 is checked against 1e-6 or five times that measured noise
+    # (the largest of 16 components), h = 1e-5 (noise and truncation both
+    # ~1e-7) against 1e-6.
+    d = np.random.default_rng(7).standard_normal(16)
+    d /= np.linalg.norm(d)
+    ts = np.arange(-4, 5) * 1e-9
+    kes = np.array([ke_of(a0 + t * d) for t in ts])
+    dke = kes - kes[4]  # exact (Sterbenz); the fit then works on ~1e-10 values
+    resid = dke - np.polyval(np.polyfit(ts / 1e-9, dke, 2), ts / 1e-9)
+    sigma = np.sqrt(np.sum(resid ** 2) / (len(ts) - 3))
     errs = {}
     for h in (1e-6, 1e-5):
         g_fd = np.zeros(16)
@@ -262,11 +273,12 @@ def test_gradient_512_vs_finite_differences_and_cost():
             e[k] = h
             g_fd[k] = (ke_of(a0 + e) - ke_of(a0 - e)) / (2 * h)
         errs[h] = np.abs(g_adj - g_fd).max() / np.abs(g_fd).max()
-    noise_floor = 16 * np.finfo(float).eps * ke / 1e-6 / np.abs(g_adj).max()
-    print("adjoint 512x512: KE %.6e, max|g| %.3e, adjoint vs FD max rel %.2e (h=1e-6, noise floor "
-          "%.1e), %.2e (h=1e-5); forward %.4f s (with checkpoints %.4f s), backward %.4f s, "
-          "ratio %.2f" % (ke, np.abs(g_adj).max(), errs[1e-6], noise_floor, errs[1e-5], t_fwd,
-                          t_fwd_ckpt, t_bwd, t_bwd / t_fwd))
+    noise_floor = 5 * sigma / (np.sqrt(2) * 1e-6) / np.abs(g_adj).max()
+    print("adjoint 512x512: KE %.6e (rounding noise %.1e = %.1f ulp), max|g| %.3e, adjoint vs FD "
+          "max rel %.2e (h=1e-6, measured noise floor %.1e), %.2e (h=1e-5); forward %.4f s (with "
+          "checkpoints %.4f s), backward %.4f s, ratio %.2f"
+          % (ke, sigma, sigma / np.spacing(ke), np.abs(g_adj).max(), errs[1e-6], noise_floor,
+             errs[1e-5], t_fwd, t_fwd_ckpt, t_bwd, t_bwd / t_fwd))
     assert errs[1e-6] <= max(1e-6, noise_floor), errs
     assert errs[1e-5] <= 1e-6, errs
     assert t_bwd <= 3.0 * t_fwd, (t_bwd, t_fwd)
