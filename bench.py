@@ -743,6 +743,41 @@ def run_ablations(args, torch) -> list:
     return out
 
 
+def run_variants(args, torch) -> list:
+    """The split stages with each alternative kernel on the headline lattice:
+    propagate direct / staged through LDS / with 16-byte accesses (FP64 and
+    shifted FP32), collide on the vector units / on the FP64 matrix cores.
+    --warmup untimed split steps, then --steps timed ones per kernel set
+    (HIP events around every stage on the kernels' stream); one record per
+    set.  For the design comparison and its kernel trace."""
+    from paper_1703_00186_amd import workload
+    from paper_1703_00186_amd.lb import LB
+
+    lx, ly = args.lx, args.ly
+    sites = lx * ly
+    fields = workload.rt_fields(lx, ly, seed=workload.config_seed(2))[:4]
+    out = []
+    for prec in ("fp64", "fp32s"):
+        for kernel in ("split", "split_lds", "split_wide", "split_mfma"):
+            if kernel == "split_mfma" and prec != "fp64":
+                continue
+            lb = LB(lx, ly, *fields, precision=prec, layout=args.layout, kernel=kernel)
+            time_split_kernels(lb, args.warmup, torch)
+            sp = time_split_kernels(lb, args.steps, torch)
+            bps = bytes_per_site(prec)
+            rec = {"kernel": kernel, "precision": prec, "lattice": [lx, ly],
+                   "steps": args.steps, "layout": args.layout}
+            for stage in ("propagate", "collide"):
+                rec[stage + "_ms"] = round(sp[stage] * 1e3, 5)
+                rec[stage + "_GB/s"] = round(bps * sites / sp[stage] / 1e9, 1)
+            rec["step_MLUPS"] = round(mlups(sites, sum(sp.values())), 1)
+            out.append(rec)
+            log("variants: %s" % rec)
+            del lb
+            torch.cuda.empty_cache()
+    return out
+
+
 def run_forms(args, torch) -> list:
     """Only the fused step of each named storage form on the headline lattice:
     --warmup untimed steps, then --steps timed ones (HIP events on the
@@ -822,6 +857,9 @@ def main(argv=None) -> int:
                     choices=["fp64", "fp32l", "fp32c", "fp32s", "fp32s_f32sum"],
                     help="time only the fused step of these storage forms on the headline "
                          "lattice (one JSON record each; for profiles)")
+    ap.add_argument("--variants", action="store_true",
+                    help="time the split stages with each alternative kernel (LDS-staged and "
+                         "16-byte propagate, matrix-core collide)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scale reference)")
     args = ap.parse_args(argv)
@@ -839,6 +877,12 @@ def main(argv=None) -> int:
 
     if args.rt_run:
         print(json.dumps(run_rt(args, torch)), flush=True)
+        return 0
+    if args.variants:
+        for rec in run_variants(args, torch):
+            print(json.dumps(rec), flush=True)
+        if args.copy_calibration:
+            copy_calibration(torch)
         return 0
     if args.forms:
         for rec in run_forms(args, torch):

@@ -88,9 +88,20 @@ extern "C" {
 #define LB_LAYOUT_SOA 0    /* l*NX*NY + X*NY + Y   (the paper's layout, Sec. 4) */
 #define LB_LAYOUT_COLUMN 1 /* X*37*NY + l*NY + Y   (all populations of a column */
                            /*  contiguous)                                      */
-/* lb_params.kernel */
-#define LB_KERNEL_FUSED 0 /* one kernel per step: propagate+bc+collide        */
-#define LB_KERNEL_SPLIT 1 /* halo, propagate, bc, collide as separate kernels */
+/* lb_params.kernel.  The three SPLIT_* values run the split stages with one
+ * stage replaced by an alternative kernel (same results: propagate bit for
+ * bit, collide to FP64 rounding), kept to measure the main kernels' design
+ * against: propagate with each population's source window (the tile's rows
+ * and the three-row halo, Sec. 2) staged through LDS; propagate with 16-byte
+ * accesses (two FP64 / four FP32 sites per thread); the FP64 collide with
+ * the Hermite projection and reconstruction (Sec. 2) as dense products on the
+ * FP64 matrix cores (LB_FP64 only).  The local-reference forms run
+ * LB_KERNEL_FUSED only. */
+#define LB_KERNEL_FUSED 0      /* one kernel per step: propagate+bc+collide        */
+#define LB_KERNEL_SPLIT 1      /* halo, propagate, bc, collide as separate kernels */
+#define LB_KERNEL_SPLIT_LDS 2  /* split, propagate staged through LDS              */
+#define LB_KERNEL_SPLIT_WIDE 3 /* split, propagate with 16-byte accesses           */
+#define LB_KERNEL_SPLIT_MFMA 4 /* split, collide on the FP64 matrix cores          */
 
 typedef struct lb_lattice {
   int32_t lx;        /* physical sites along x (periodic), 6 .. 2^22    */
@@ -109,7 +120,7 @@ typedef struct lb_params {
   double t_top;        /* wall temperature above row ly-1                      */
   double rho_ref;      /* shift density of the FP32 modes (ignored for FP64)   */
   int32_t regularize;  /* 1: Hermite projection of the collision, 0: plain BGK */
-  int32_t kernel;      /* LB_KERNEL_FUSED or LB_KERNEL_SPLIT                   */
+  int32_t kernel;      /* LB_KERNEL_FUSED, LB_KERNEL_SPLIT or a SPLIT_* variant */
   int32_t check_finite; /* 0: off; N > 0: every N steps lb_step scans the state */
                         /* and returns LB_E_NONFINITE if rho<=0, T<=0 or NaN   */
   int32_t reserved;     /* must be 0                                           */
@@ -118,8 +129,9 @@ typedef struct lb_params {
 typedef struct lb_ctx lb_ctx;
 
 const char* lb_last_error(void);
-/* Interface version: 4 (3: adjoint arrays in the lattice's layout and
- * lb_adjoint_run; 4: precisions LB_FP32_COLLIDE and LB_FP32_LOCAL). */
+/* Interface version: 5 (3: adjoint arrays in the lattice's layout and
+ * lb_adjoint_run; 4: precisions LB_FP32_COLLIDE and LB_FP32_LOCAL;
+ * 5: kernels LB_KERNEL_SPLIT_LDS, _WIDE and _MFMA). */
 int lb_version(void);
 
 /* Bytes of device workspace lb_init needs for this lattice (two padded
@@ -183,6 +195,8 @@ int lb_get_populations(lb_ctx* ctx, double* f);
  *   lb_bc:        applies the thermal walls to B in place (rows 0..2 and
  *                 ly-3..ly-1; no-op for LB_Y_PERIODIC).
  *   lb_collide:   A = collide(B), site by site.
+ * lb_propagate and lb_collide run the alternative kernel of the context's
+ * LB_KERNEL_SPLIT_* value where it names one (lb_step's split path too).
  * lb_get_scratch / lb_set_scratch copy B's physical region in the compact
  * form of lb_get_state. */
 int lb_halo(lb_ctx* ctx);

@@ -16,8 +16,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libd2q37_lb.so")
-SOURCES = [os.path.join(CSRC, "d2q37_kernels.hip"), os.path.join(CSRC, "lb_api.hip"),
-           os.path.join(CSRC, "lb_scratch.hip")]
+SOURCES = [os.path.join(CSRC, "d2q37_kernels.hip"), os.path.join(CSRC, "d2q37_variants.hip"),
+           os.path.join(CSRC, "lb_api.hip"), os.path.join(CSRC, "lb_scratch.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -37,6 +37,15 @@ hipError_t launch_bc(void* buf, const Geom& g, const Phys& p, int prec, hipStrea
 hipError_t launch_collide(const void* src, void* dst, const Geom& g, const Phys& p, int prec,
                           int regularize, hipStream_t s);
 
+// Alternative split-stage kernels (d2q37_variants.hip), same results:
+// propagate staged through LDS or with 16-byte accesses (FP64 and the
+// shifted FP32 forms), and the FP64 collide on the matrix cores.
+enum PropagateVariant { kPropagateLds = 1, kPropagateWide = 2 };
+hipError_t launch_propagate_variant(const void* src, void* dst, const Geom& g, int prec,
+                                    int variant, hipStream_t s);
+hipError_t launch_collide_mfma(const void* src, void* dst, const Geom& g, const Phys& p,
+                               int regularize, hipStream_t s);
+
 // dst = f^eq(rho0, u0, T0) (shifted by w rho_ref for FP32), physical region.
 hipError_t launch_init_feq(void* dst, const double* rho, const double* ux, const double* uy,
                            const double* T, const Geom& g, const Phys& p, int prec,

@@ -98,7 +98,7 @@ int check_params(const lb_params* par) {
     return fail(LB_E_ARG, "wall temperatures must be finite and > 0%s");
   if (!std::isfinite(par->rho_ref)) return fail(LB_E_ARG, "rho_ref not finite%s");
   if (par->regularize != 0 && par->regularize != 1) return fail(LB_E_ARG, "regularize must be 0 or 1%s");
-  if (par->kernel != LB_KERNEL_FUSED && par->kernel != LB_KERNEL_SPLIT)
+  if (par->kernel < LB_KERNEL_FUSED || par->kernel > LB_KERNEL_SPLIT_MFMA)
     return fail(LB_E_ARG, "unknown kernel%s");
   if (par->check_finite < 0) return fail(LB_E_ARG, "check_finite must be >= 0%s");
   if (par->reserved != 0) return fail(LB_E_ARG, "params.reserved must be 0%s");
@@ -147,7 +147,27 @@ size_t buffer_bytes(const Geom& g, int prec) {
 int check_kernel(int prec, const lb_params& par) {
   if (is_local_form(prec) && par.kernel != LB_KERNEL_FUSED)
     return fail(LB_E_ARG, "LB_FP32_COLLIDE and LB_FP32_LOCAL run the fused kernel only%s");
+  if (par.kernel == LB_KERNEL_SPLIT_MFMA && prec != LB_FP64)
+    return fail(LB_E_ARG, "LB_KERNEL_SPLIT_MFMA needs LB_FP64%s");
   return LB_OK;
+}
+
+// The split stages, with the alternative kernel the context's kernel value
+// names (same results as the main ones).
+hipError_t propagate_stage(lb_ctx* c) {
+  if (c->par.kernel == LB_KERNEL_SPLIT_LDS)
+    return d2q37::launch_propagate_variant(c->A, c->B, c->g, c->prec, d2q37::kPropagateLds,
+                                           c->stream);
+  if (c->par.kernel == LB_KERNEL_SPLIT_WIDE)
+    return d2q37::launch_propagate_variant(c->A, c->B, c->g, c->prec, d2q37::kPropagateWide,
+                                           c->stream);
+  return d2q37::launch_propagate(c->A, c->B, c->g, c->prec, c->stream);
+}
+
+hipError_t collide_stage(lb_ctx* c) {
+  if (c->par.kernel == LB_KERNEL_SPLIT_MFMA)
+    return d2q37::launch_collide_mfma(c->B, c->A, c->g, c->p, c->par.regularize, c->stream);
+  return d2q37::launch_collide(c->B, c->A, c->g, c->p, c->prec, c->par.regularize, c->stream);
 }
 
 int no_split_stage(lb_ctx* ctx, const char* what) {
@@ -216,10 +236,9 @@ int one_step(lb_ctx* c, double* tape) {
   } else {
     int rc = do_halo(c);
     if (rc) return rc;
-    LB_HIP(d2q37::launch_propagate(c->A, c->B, c->g, c->prec, c->stream), "propagate");
+    LB_HIP(propagate_stage(c), "propagate");
     LB_HIP(d2q37::launch_bc(c->B, c->g, c->p, c->prec, c->stream), "bc");
-    LB_HIP(d2q37::launch_collide(c->B, c->A, c->g, c->p, c->prec, c->par.regularize, c->stream),
-           "collide");
+    LB_HIP(collide_stage(c), "collide");
     c->halos_valid = false;
   }
   if (c->par.check_finite > 0 && ++c->steps_since_check >= c->par.check_finite) {
@@ -283,7 +302,7 @@ extern "C" {
 
 const char* lb_last_error(void) { return g_error.c_str(); }
 
-int lb_version(void) { return 4; }
+int lb_version(void) { return 5; }
 
 int lb_workspace_bytes(const lb_lattice* lat, const lb_params* par, size_t* bytes) {
   int rc = check_lattice(lat);
@@ -432,7 +451,7 @@ int lb_propagate(lb_ctx* ctx) {
   if (rc) return rc;
   rc = no_split_stage(ctx, "lb_propagate");
   if (rc) return rc;
-  LB_HIP(d2q37::launch_propagate(ctx->A, ctx->B, ctx->g, ctx->prec, ctx->stream), "propagate");
+  LB_HIP(propagate_stage(ctx), "propagate");
   return LB_OK;
 }
 
@@ -450,9 +469,7 @@ int lb_collide(lb_ctx* ctx) {
   if (rc) return rc;
   rc = no_split_stage(ctx, "lb_collide");
   if (rc) return rc;
-  LB_HIP(d2q37::launch_collide(ctx->B, ctx->A, ctx->g, ctx->p, ctx->prec, ctx->par.regularize,
-                               ctx->stream),
-         "collide");
+  LB_HIP(collide_stage(ctx), "collide");
   ctx->halos_valid = false;
   return LB_OK;
 }

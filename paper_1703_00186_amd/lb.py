@@ -29,6 +29,9 @@ LOCAL_FORMS = ("fp32c", "fp32l")
 LB_Y_WALLS, LB_Y_PERIODIC = 0, 1
 LB_LAYOUT_SOA, LB_LAYOUT_COLUMN = 0, 1
 LB_KERNEL_FUSED, LB_KERNEL_SPLIT = 0, 1
+LB_KERNEL_SPLIT_LDS, LB_KERNEL_SPLIT_WIDE, LB_KERNEL_SPLIT_MFMA = 2, 3, 4
+KERNELS = {"fused": LB_KERNEL_FUSED, "split": LB_KERNEL_SPLIT, "split_lds": LB_KERNEL_SPLIT_LDS,
+           "split_wide": LB_KERNEL_SPLIT_WIDE, "split_mfma": LB_KERNEL_SPLIT_MFMA}
 
 ERRORS = {-1: "LB_E_ARG", -2: "LB_E_WORKSPACE", -3: "LB_E_HIP", -4: "LB_E_STATE",
           -5: "LB_E_NONFINITE"}
@@ -135,7 +138,7 @@ def _ptr(t) -> ctypes.c_void_p:
 
 def make_params(tau=0.7, g=(0.0, -1e-4), t_bottom=1.5, t_top=0.5, rho_ref=1.0, regularize=1,
                 kernel="fused", check_finite=0) -> Params:
-    k = {"fused": LB_KERNEL_FUSED, "split": LB_KERNEL_SPLIT}[kernel]
+    k = KERNELS[kernel]
     return Params(float(tau), float(g[0]), float(g[1]), float(t_bottom), float(t_top),
                   float(rho_ref), int(regularize), k, int(check_finite), 0)
 

@@ -41,6 +41,11 @@ void check_context(int precision, int layout, int kernel, int ybc) {
     EXPECT(lb_workspace_bytes(&lat, &par, &need) == LB_E_ARG);
     return;
   }
+  if (kernel == LB_KERNEL_SPLIT_MFMA && precision != LB_FP64) {  // FP64 matrix cores only
+    EXPECT(lb_workspace_bytes(&lat, &par, &need) == LB_E_ARG);
+    EXPECT(std::string(lb_last_error()).find("LB_FP64") != std::string::npos);
+    return;
+  }
   EXPECT(lb_workspace_bytes(&lat, &par, &need) == LB_OK);
   EXPECT(need >= 2 * (local ? 38 : 37) * S * (precision == LB_FP64 ? 8 : 4));
   void* ws = std::aligned_alloc(256, round256(need) + 256);
@@ -149,7 +154,7 @@ void check_context(int precision, int layout, int kernel, int ybc) {
 }  // namespace
 
 int main() {
-  EXPECT(lb_version() == 4);
+  EXPECT(lb_version() == 5);
   lb_lattice lat = {64, 48, LB_FP64, LB_Y_WALLS, LB_LAYOUT_COLUMN, 0};
   lb_params par = {0.7, 0.0, -1e-4, 1.5, 0.5, 1.0, 1, LB_KERNEL_FUSED, 0, 0};
   size_t need = 0;
@@ -206,7 +211,8 @@ int main() {
   for (int prec : {LB_FP64, LB_FP32_SHIFTED, LB_FP32_SHIFTED_F32SUM, LB_FP32_COLLIDE,
                    LB_FP32_LOCAL})
     for (int layout : {LB_LAYOUT_SOA, LB_LAYOUT_COLUMN})
-      for (int kernel : {LB_KERNEL_FUSED, LB_KERNEL_SPLIT})
+      for (int kernel : {LB_KERNEL_FUSED, LB_KERNEL_SPLIT, LB_KERNEL_SPLIT_LDS,
+                         LB_KERNEL_SPLIT_WIDE, LB_KERNEL_SPLIT_MFMA})
         for (int ybc : {LB_Y_WALLS, LB_Y_PERIODIC}) check_context(prec, layout, kernel, ybc);
 
   EXPECT(lb_step(nullptr, 1) == LB_E_ARG);

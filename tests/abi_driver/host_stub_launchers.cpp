@@ -16,6 +16,12 @@ hipError_t launch_propagate(const void*, void*, const Geom&, int, hipStream_t) {
   return hipSuccess;
 }
 hipError_t launch_bc(void*, const Geom&, const Phys&, int, hipStream_t) { return hipSuccess; }
+hipError_t launch_propagate_variant(const void*, void*, const Geom&, int, int, hipStream_t) {
+  return hipSuccess;
+}
+hipError_t launch_collide_mfma(const void*, void*, const Geom&, const Phys&, int, hipStream_t) {
+  return hipSuccess;
+}
 hipError_t launch_collide(const void*, void*, const Geom&, const Phys&, int, int, hipStream_t) {
   return hipSuccess;
 }

@@ -65,7 +65,8 @@ def test_lattice_validation(lib, bad):
 
 
 @pytest.mark.parametrize("bad", [dict(tau=0.5), dict(tau=float("nan")), dict(t_top=0.0),
-                                 dict(regularize=2), dict(kernel=5), dict(check_finite=-1)])
+                                 dict(regularize=2), dict(kernel=5), dict(kernel=-1),
+                                 dict(check_finite=-1)])
 def test_params_validation(lib, bad):
     lat = lbmod.make_lattice(64, 64)
     par = lbmod.make_params()
@@ -117,7 +118,7 @@ def test_largest_lattice_is_accepted(lib):
 
 
 def test_version(lib):
-    assert lib.lb_version() == 4
+    assert lib.lb_version() == 5
 
 
 def test_binding_refuses_to_run_without_the_hip_library(monkeypatch, tmp_path):
