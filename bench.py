@@ -282,6 +282,43 @@ def fp32_legs(lx: int, ly: int, fields, layout: str, fp64_mlups: float, torch) -
     return out
 
 
+def precision_leg(torch, layout: str = "column") -> dict:
+    """The precision workload's lattice, 4096 x 4096 (sinusoidal RT): the FP64
+    step and each FP32 form timed over FP32_TIMED steps after FP32_WARMUP
+    (the FP32 MLUPS over the FP64 MLUPS of this lattice), every run carried
+    on to FP32_ERROR_STEPS steps and the FP32 fields compared with the FP64
+    GPU run's."""
+    from paper_1703_00186_amd import workload
+    from paper_1703_00186_amd.lb import LB
+
+    lx, ly = 4096, 4096
+    sites = lx * ly
+    fields = workload.rt_fields(lx, ly, seed=workload.config_seed(3))[:4]
+    rec = {"lattice": [lx, ly], "steps_timed": FP32_TIMED, "warmup": FP32_WARMUP,
+           "error_after_steps": FP32_ERROR_STEPS}
+    m64 = None
+    for prec in ("fp64", "fp32c", "fp32l", "fp32s"):
+        torch.cuda.empty_cache()
+        lb = LB(lx, ly, *fields, precision=prec, layout=layout)
+        lb.step(FP32_WARMUP)
+        t = time_steps(lb, FP32_TIMED, torch)
+        lb.step(FP32_ERROR_STEPS - FP32_WARMUP - FP32_TIMED)
+        v = mlups(sites * FP32_TIMED, t)
+        gbs = bytes_per_site(prec) * sites / (t / FP32_TIMED) / 1e9
+        rec[prec] = {"MLUPS": round(v, 1), "ms_per_step": round(t / FP32_TIMED * 1e3, 4),
+                     "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        if prec == "fp64":
+            m64 = host_moments(lb, torch)
+        else:
+            errs = field_errors(host_moments(lb, torch), m64)
+            rec[prec]["ratio_vs_fp64"] = round(v / rec["fp64"]["MLUPS"], 3)
+            rec[prec]["error_vs_fp64_gpu"] = {k: float("%.3g" % e) for k, e in errs.items()}
+        log("bench: 4096x4096 %s %s" % (prec, rec[prec]))
+        del lb
+    torch.cuda.empty_cache()
+    return rec
+
+
 def production_leg(torch, steps: int = 200, warmup: int = 10, n_adj: int = 100,
                    k: int = 20) -> dict:
     """The production lattice, 8192 x 4096 (multimode RT): FP64 and FP32 step
@@ -951,6 +988,7 @@ def main(argv=None) -> int:
         del lb
         torch.cuda.empty_cache()
         out.update(fp32_legs(lx, ly, fields, args.layout, value, torch))
+        out["precision_4096x4096"] = precision_leg(torch, args.layout)
         out["production_8192x4096"] = production_leg(torch)
     if not args.no_extras:
         # launch-bound small lattice: eager launches vs one graph of 100 steps

@@ -113,10 +113,9 @@ __device__ __forceinline__ void project(const A (&f)[Q], A (&a)[5][5]) {
 }
 
 // ---------------------------------------------------------------------------
-// reconstruct: f_l = w_l sum_pq b_pq He_p(c_lx) He_q(c_ly) / (p! q!), over the
-// Hermite orders p + q >= kMinOrder (the lower ones are left out).
+// reconstruct: f_l = w_l sum_pq b_pq He_p(c_lx) He_q(c_ly) / (p! q!).
 // ---------------------------------------------------------------------------
-template <class A, int kMinOrder = 0>
+template <class A>
 __device__ __forceinline__ void reconstruct(const A (&b)[5][5], A (&f)[Q]) {
 #pragma unroll
   for (int ex = 3; ex >= -3; --ex) {
@@ -128,7 +127,7 @@ __device__ __forceinline__ void reconstruct(const A (&b)[5][5], A (&f)[Q]) {
 #pragma unroll
       for (int p = 0; p + q < 5; ++p) {
         const double hp = hef(ex, p);
-        if (hp == 0.0 || p + q < kMinOrder) continue;
+        if (hp == 0.0) continue;
         if (hp == 1.0)
           s += b[p][q];
         else
@@ -418,8 +417,7 @@ __device__ __forceinline__ unsigned encode_site(const double (&f)[Q], float (&g)
 //      b_pq = (1 - 1/tau) a^n_pq + (a^eq_pq - a^M_pq) / tau in FP64, rounded
 //      once to FP32 (a^M: a_00 = rho_s, a_20 = a_02 = rho_s th_s,
 //      a_40 = a_04 = 3 rho_s th_s^2, a_22 = rho_s th_s^2, the others 0);
-//   5. g_l = w_l sum_pq b_pq H_pq(c_l) / (p! q!) in FP32, the orders 0 and 1
-//      (mass and momentum) reconstructed on their own and added last;
+//   5. g_l = w_l sum_pq b_pq H_pq(c_l) / (p! q!) in FP32;
 //   6. conservation: the invariants of the FP32 values g are summed in FP64
 //      and their shortfall against b_00, b_10, b_01, b_20 + b_02 (exact) is
 //      put into the five populations (0,0), (+-1,0), (0,+-1) (in FP32
@@ -515,14 +513,9 @@ __device__ __forceinline__ unsigned collide_site_local(const double (&f)[Q], flo
   }
   // 5. FP32 reconstruction of the deviation
   float r[Q];
-  reconstruct<float, 2>(b, r);
+  reconstruct<float>(b, r);
 #pragma unroll
-  for (int l = 0; l < Q; ++l) {
-    float r1 = float(W[l]) * b[0][0];
-    if (EX[l] != 0) r1 += float(W[l] * R * EX[l]) * b[1][0];
-    if (EY[l] != 0) r1 += float(W[l] * R * EY[l]) * b[0][1];
-    g[l] = kRegularize ? r1 + r[l] : float(keep) * n[l] + (r1 + r[l]);
-  }
+  for (int l = 0; l < Q; ++l) g[l] = kRegularize ? r[l] : float(keep) * n[l] + r[l];
   // 6. conservation correction
   double cf[kFamilies], cx[7], cy[7];
 #pragma unroll
