@@ -549,6 +549,16 @@ def _adjoint_workload(torch) -> dict:
         lb.step(n)
         return float(lb.loss_ke(with_lambda=False)[0].cpu()[0])
 
+    # rounding noise of KE: nine points of a line through the amplitudes
+    # (|t| <= 4e-9) minus their least-squares quadratic; a central
+    # difference at h carries sigma / (sqrt(2) h) per component
+    d = np.random.default_rng(7).standard_normal(16)
+    d /= np.linalg.norm(d)
+    ts = np.arange(-4, 5) * 1e-9
+    kes = np.array([ke_of(info["amplitudes"] + t * d) for t in ts])
+    dke = kes - kes[4]
+    resid = dke - np.polyval(np.polyfit(ts / 1e-9, dke, 2), ts / 1e-9)
+    sigma = float(np.sqrt(np.sum(resid ** 2) / (len(ts) - 3)))
     fd = {}
     for h in (1e-6, 1e-5):
         gfd = np.zeros(16)
@@ -573,11 +583,12 @@ def _adjoint_workload(torch) -> dict:
     rec = {"workload": "adjoint 512x512", "lattice": [lx, ly], "steps": n, "checkpoint_every": k,
            "KE": float(ke.detach().cpu()), "max_abs_grad": float(np.abs(g).max()),
            "adjoint_vs_central_fd": fd,
-           # rounding noise of a central difference: ~16 ulps of KE over h,
-           # relative to max |dKE/da|; at h = 1e-6 it is the size of the
+           # measured rounding noise of KE and of a central difference at h,
+           # relative to max |dKE/da|: at h = 1e-6 it is the size of the
            # difference itself (h = 1e-5 is below both noise and truncation)
-           "fd_noise_floor": {"%g" % h: float(16 * np.finfo(float).eps * float(ke.detach().cpu())
-                                              / h / np.abs(g).max()) for h in (1e-6, 1e-5)},
+           "ke_rounding_noise": sigma,
+           "fd_noise_per_component": {"%g" % h: float(sigma / (np.sqrt(2) * h) / np.abs(g).max())
+                                      for h in (1e-6, 1e-5)},
            "forward_s": round(t_plain, 5),
            "forward_with_checkpoints_s": round(t1 - t0, 5), "backward_s": round(t2 - t1, 5),
            "backward_over_forward": round((t2 - t1) / t_plain, 3),

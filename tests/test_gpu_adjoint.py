@@ -105,6 +105,32 @@ def test_adjoint_run_equals_single_steps(ybc, regularize, layout, shape, n):
     assert torch.equal(again, lam0)
 
 
+def test_adjoint_run_equals_single_steps_production_size():
+    """The production lattice, 8192 x 4096 (gather form over two 10 GB padded
+    buffers): lb_adjoint_run over 3 recorded steps of the multimode RT run
+    equals 3 lb_adjoint_step calls bit for bit, starting from the kinetic
+    energy's lambda."""
+    lx, ly, n = 8192, 4096, 3
+    rho, ux, uy, T, _ = workload.rt_fields(lx, ly, seed=workload.config_seed(5),
+                                           mode="multimode")
+    lb = LB(lx, ly, rho, ux, uy, T)
+    lb.step(5)
+    tape = lb.new_tape(n)
+    lb.step_record(n, tape)
+    _, lam0 = lb.loss_ke(with_lambda=True)
+    ref, spare = lam0.clone(), lb.new_lambda()
+    for j in range(n - 1, -1, -1):
+        lb.adjoint_step(tape[j], ref, spare)
+        ref, spare = spare, ref
+    del spare
+    got = lam0.clone()
+    del lam0
+    lb.adjoint_run(tape, got, n)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(got).all())
+    assert torch.equal(got, ref), float((got - ref).abs().max())
+
+
 def test_tape_holds_pre_collision_moments():
     lx, ly = 24, 20
     lb, P, f, _ = setup(lx, ly)
