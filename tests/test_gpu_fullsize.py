@@ -72,3 +72,29 @@ def test_one_step_at_sampled_sites(lx, ly, precision, mode, warm):
     assert err <= tol
     del lb
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kernel,precision", [
+    ("split", "fp64"), ("split_lds", "fp64"), ("split_wide", "fp64"), ("split_mfma", "fp64"),
+    ("split", "fp32s"), ("split_lds", "fp32s"), ("split_wide", "fp32s")])
+def test_split_stage_kernels_at_sampled_sites(kernel, precision):
+    """The split path and its alternative stage kernels on the 1920 x 2048
+    lattice that `bench.py --variants` times: one step at sampled sites
+    against the oracle."""
+    lx, ly = 1920, 2048
+    f = workload.rt_fields(lx, ly, seed=workload.config_seed(2))[:4]
+    lb = LB(lx, ly, *f, precision=precision, kernel=kernel)
+    lb.step(20)
+    state = lb.populations().cpu().numpy()
+    lb.step(1)
+    torch.cuda.synchronize()
+    nxt = lb.populations().cpu().numpy()
+    xs, ys = sample_sites(lx, ly)
+    ref = oracle.step_sites(state, oparams(), xs, ys)
+    got = nxt[:, xs, ys].T
+    tol = {"fp64": 1e-13, "fp32s": 3e-7}[precision]
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("%s %s 1920x2048 one step at %d sampled sites: %.2e" % (kernel, precision, len(xs), err))
+    assert err <= tol
+    del lb
+    torch.cuda.empty_cache()
