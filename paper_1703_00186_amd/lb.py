@@ -155,6 +155,11 @@ class LB:
 
     Initial fields rho0, ux0, uy0, T0 are [lx, ly] float64 (numpy or torch);
     they are copied to the device and the state starts at f^eq(rho0, u0, T0).
+    precision: one of PRECISIONS ("fp64", "fp32c", "fp32l", "fp32s",
+    "fp32s_f32sum"); params: those of make_params (tau, g, t_bottom, t_top,
+    rho_ref, regularize, kernel, check_finite), kernel one of KERNELS
+    ("fused"; "split"; "split_lds", "split_wide", "split_mfma": the split
+    stages with an alternative propagate or collide kernel).
     """
 
     def __init__(self, lx, ly, rho0, ux0, uy0, T0, *, precision="fp64", ybc="walls",
