@@ -31,6 +31,8 @@
  *    the GPU except lb_step with check_finite > 0.  The caller synchronises
  *    before reading results.  Errors of already-enqueued work surface as
  *    LB_E_HIP at a later call (sticky).
+ *  - A context belongs to the HIP device current at lb_init; every later call
+ *    on it must be made with that device current (else LB_E_STATE).
  *  - A context is not thread-safe; distinct contexts are independent.
  */
 #ifndef D2Q37_LB_H

@@ -19,6 +19,9 @@ enum Precision {
   kF32Local = 4
 };
 
+// The current HIP device (hipGetDevice).
+hipError_t current_device(int* dev);
+
 // Fill `bytes` (multiple of 4) of device memory with zero.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 

@@ -15,6 +15,7 @@ using d2q37::Geom;
 using d2q37::Phys;
 
 struct lb_ctx {
+  int device;  // the HIP device current at lb_init: every launch goes there
   lb_lattice lat;
   lb_params par;
   Geom g;
@@ -188,8 +189,21 @@ size_t observable_bytes(const Geom& g) {
                    size_t(d2q37::kObservableScalars)) * sizeof(double), kAlign);
 }
 
+// A context's buffers and stream live on the device that was current at
+// lb_init, and kernels launch on the current device: refuse a call made with
+// another device current instead of launching there.
 int check_ctx(lb_ctx* ctx) {
   if (!ctx) return fail(LB_E_ARG, "context is NULL%s");
+  int dev = -1;
+  const hipError_t e = d2q37::current_device(&dev);
+  if (e != hipSuccess) return hip_fail(e, "current device");
+  if (dev != ctx->device) {
+    char buf[160];
+    std::snprintf(buf, sizeof(buf),
+                  "the context belongs to device %d but device %d is current", ctx->device, dev);
+    g_error = buf;
+    return LB_E_STATE;
+  }
   return LB_OK;
 }
 
@@ -332,8 +346,11 @@ int lb_init(const lb_lattice* lat, const lb_params* par, void* workspace, size_t
   if (!rho0 || !ux0 || !uy0 || !T0) return fail(LB_E_ARG, "initial fields must not be NULL%s");
   if (lat->precision != LB_FP64 && !(par->rho_ref >= 0))
     return fail(LB_E_ARG, "rho_ref must be >= 0%s");
+  int dev = -1;
+  LB_HIP(d2q37::current_device(&dev), "current device");
   lb_ctx* c = new (std::nothrow) lb_ctx;
   if (!c) return fail(LB_E_ARG, "out of host memory%s");
+  c->device = dev;
   c->lat = *lat;
   c->par = *par;
   c->prec = lat->precision;

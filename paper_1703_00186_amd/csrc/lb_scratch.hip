@@ -1,4 +1,8 @@
-// The per-GPU static scratch of lb_adjoint_run_static: device memory for the
+// Device-runtime helpers of the C ABI (kept out of lb_api.hip so that its host
+// logic can be built and checked without a GPU, with these stubbed): the
+// current device, and the per-GPU static scratch of lb_adjoint_run_static.
+//
+// The static scratch: device memory for the
 // two padded FP64 adjoint buffers that callers who cannot allocate do not
 // pass in.  Each GPU the library runs on holds its own copy of the array for
 // the life of the process.  In host code `scratch` names a host-side
@@ -23,6 +27,8 @@ std::mutex g_mutex;
 void* g_address[kMaxDevices] = {};
 
 }  // namespace
+
+hipError_t current_device(int* dev) { return hipGetDevice(dev); }
 
 hipError_t static_scratch(void** out) {
   int dev = -1;

@@ -15,6 +15,10 @@
 
 #include "lb.h"
 
+namespace d2q37 {
+extern int g_stub_device;  // host_stub_launchers.cpp
+}
+
 namespace {
 
 int failures = 0;
@@ -103,6 +107,12 @@ void check_context(int precision, int layout, int kernel, int ybc) {
   p2.kernel = kernel;
   EXPECT(lb_set_params(ctx, &p2) == LB_OK);
   EXPECT(lb_step(ctx, 2) == LB_OK);
+  // a call made with another device current is refused, not launched there
+  d2q37::g_stub_device = 1;
+  EXPECT(lb_step(ctx, 1) == LB_E_STATE);
+  EXPECT(std::string(lb_last_error()).find("belongs to device 0") != std::string::npos);
+  d2q37::g_stub_device = 0;
+  EXPECT(lb_step(ctx, 1) == LB_OK);
 
   double ke = 0.0;
   double* t = tape.data();

@@ -6,6 +6,11 @@
 
 namespace d2q37 {
 
+int g_stub_device = 0;  // the "current device" the stubbed runtime reports
+hipError_t current_device(int* dev) {
+  *dev = g_stub_device;
+  return hipSuccess;
+}
 hipError_t launch_zero(void*, size_t, hipStream_t) { return hipSuccess; }
 hipError_t launch_halo(void*, const Geom&, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_fused(const void*, void*, const Geom&, const Phys&, int, int, double*,
