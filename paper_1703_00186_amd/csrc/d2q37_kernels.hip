@@ -926,9 +926,11 @@ hipError_t launch_fused(const void* src, void* dst, const Geom& g, const Phys& p
     const dim3 grid(t.nb), block(kThreads);
     if constexpr (is_local<A>) {
       // column layout: buffer-addressed kernel (its per-tile resources span
-      // a few columns); SoA: planes lie a lattice apart, global addressing
+      // bx + 6 columns, which must fit the 32-bit byte range of a buffer
+      // resource); SoA, or columns too tall for that: global addressing
       constexpr bool k64 = A::f64_collide;
-      const bool column = g.ps < g.cs;
+      const bool column = g.ps < g.cs &&
+                          (long long)(t.bx + 2 * HX) * g.cs * (long long)sizeof(float) < (1LL << 32);
       if (column && regularize)
         hipLaunchKernelGGL((k_fused_local_col<true, k64>), grid, block, 0, s, a, b, g, p, t.by,
                            t.bx, t.nty, t.nb);

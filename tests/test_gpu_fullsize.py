@@ -98,3 +98,35 @@ def test_split_stage_kernels_at_sampled_sites(kernel, precision):
     assert err <= tol
     del lb
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp32l"])
+def test_local_reference_form_at_maximum_column_height(precision):
+    """A 6 x 4,194,304 lattice: a column of the local-reference form (38
+    planes of 4,194,432 padded rows) is too tall for the 32-bit byte range of
+    the buffer resources the column-layout kernel addresses through, so the
+    step runs the globally addressed kernel; one step at sampled sites (the
+    lattice's ends, every tile boundary of the first and last 64 tiles,
+    random sites) against the oracle.  Uniform initial density (the
+    hydrostatic one would span 1e-218 .. 1e72 over 4 million rows)."""
+    lx, ly = 6, 1 << 22
+    f = workload.rt_fields(lx, ly, seed=workload.config_seed(2), mode="uniform")[:4]
+    lb = LB(lx, ly, *f, precision=precision)
+    lb.step(3)
+    state = lb.populations().cpu().numpy()
+    lb.step(1)
+    torch.cuda.synchronize()
+    nxt = lb.populations().cpu().numpy()
+    del lb
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(4)
+    ys = list(rng.integers(0, ly, 4096)) + list(range(0, 8)) + list(range(ly - 8, ly))
+    for y in list(range(255, 64 * 256, 256)) + list(range(ly - 64 * 256 + 255, ly, 256)):
+        ys += [y, min(y + 1, ly - 1)]
+    xs = np.array([i % lx for i in range(len(ys))], np.int32)
+    ys = np.array(ys, np.int32)
+    ref = oracle.step_sites(state, oparams(), xs, ys)
+    got = nxt[:, xs, ys].T
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("%s %dx%d one step at %d sampled sites: %.2e" % (precision, lx, ly, len(xs), err))
+    assert err <= 1e-7
