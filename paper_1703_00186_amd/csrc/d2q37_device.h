@@ -370,10 +370,12 @@ constexpr int kRest = 18, kEast = 11, kWest = 25, kNorth = 19, kSouth = 17;
 // packed reference
 constexpr int kLocalPlanes = Q + 1;
 
+// (the weights folded into the polynomial's compile-time coefficients, so
+// that a rebuilt population rho P_l(th) + g is three FMAs)
 __device__ __forceinline__ double rest_maxwellian(int l, double rho, double th) {
   const double x2 = c2(l);
-  const double c1 = 0.5 * (x2 - 2.0), c2q = 0.125 * (x2 * x2 - 8.0 * x2 + 8.0);
-  return (W[l] * rho) * fma(th, fma(c2q, th, c1), 1.0);
+  const double w1 = W[l] * (0.5 * (x2 - 2.0)), w2 = W[l] * (0.125 * (x2 * x2 - 8.0 * x2 + 8.0));
+  return rho * fma(th, fma(w2, th, w1), W[l]);
 }
 
 // (rho_s, th_s) <-> one 32-bit word of two FP16 numbers (rho_s low, th_s high)
