@@ -7,8 +7,12 @@ sites (Sec. 5), FP64, tau 0.7, g = 1e-4 along -y, walls at T = 1.5 / 0.5.  A
 step is one pass of the whole hot path: periodic halo, propagate, bc and
 collide, run as the fused kernel (one launch per step).  Inputs are resident
 in HBM before timing starts.  Printed: one JSON line with the headline FP64
-MLUPS, the roofline of the fused kernel, the split kernels, the FP32-shifted
-step, and the CPU oracle timed on a bounded sample on this host.
+MLUPS, the roofline of the fused kernel, the split kernels, the adjoint, the
+FP32 storage forms on this lattice and on the 4096 x 4096 precision lattice
+(each against the FP64 GPU run after 2000 steps), the 8192 x 4096 production
+lattice, a small graph-captured lattice, and the CPU oracle timed on a bounded
+sample on this host.  Other modes: --workloads, --ablations, --variants,
+--forms, --rt-run.
 """
 
 from __future__ import annotations
