@@ -130,3 +130,31 @@ def test_local_reference_form_at_maximum_column_height(precision):
     err = np.abs(got - ref).max() / np.abs(ref).max()
     print("%s %dx%d one step at %d sampled sites: %.2e" % (precision, lx, ly, len(xs), err))
     assert err <= 1e-7
+
+
+@pytest.mark.parametrize("precision,layout,regularize", [
+    ("fp64", "soa", 1), ("fp32c", "soa", 1), ("fp32l", "soa", 1),
+    ("fp64", "column", 0), ("fp32c", "column", 0), ("fp32l", "column", 0)])
+def test_layouts_and_bgk_at_sampled_sites(precision, layout, regularize):
+    """The paper's SoA layout (the local-reference forms then run their
+    globally addressed kernel) and plain BGK on the 1920 x 2048 lattice: one
+    step at sampled sites against the oracle."""
+    lx, ly = 1920, 2048
+    f = workload.rt_fields(lx, ly, seed=workload.config_seed(2))[:4]
+    lb = LB(lx, ly, *f, precision=precision, layout=layout, regularize=regularize)
+    lb.step(20)
+    state = lb.populations().cpu().numpy()
+    lb.step(1)
+    torch.cuda.synchronize()
+    nxt = lb.populations().cpu().numpy()
+    del lb
+    torch.cuda.empty_cache()
+    xs, ys = sample_sites(lx, ly)
+    P = oracle.Params(tau=0.7, gx=0.0, gy=-1e-4, t_bottom=1.5, t_top=0.5, regularize=regularize)
+    ref = oracle.step_sites(state, P, xs, ys)
+    got = nxt[:, xs, ys].T
+    tol = {"fp64": 1e-13, "fp32c": 1e-7, "fp32l": 1e-7}[precision]
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("%s %s regularize=%d 1920x2048 one step at %d sampled sites: %.2e" % (
+        precision, layout, regularize, len(xs), err))
+    assert err <= tol
