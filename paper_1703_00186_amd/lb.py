@@ -9,6 +9,7 @@ CPU fallback: if the library is missing, loading fails with an error.
 from __future__ import annotations
 
 import ctypes
+import functools
 import json
 import os
 
@@ -150,6 +151,16 @@ def make_lattice(lx, ly, precision="fp64", ybc="walls", layout="column") -> Latt
     return Lattice(int(lx), int(ly), p, y, lay, 0)
 
 
+def _on_device(method):
+    """Runs a library call with the lattice's device current (the C ABI
+    refuses calls on a context from another device)."""
+    @functools.wraps(method)
+    def wrapper(self, *args, **kwargs):
+        with torch.cuda.device(self.device):
+            return method(self, *args, **kwargs)
+    return wrapper
+
+
 class LB:
     """One D2Q37 lattice on one GPU.
 
@@ -250,6 +261,7 @@ class LB:
         self._expect(lam, self.lambda_shape, torch.float64, "adjoint array")
 
     # -- the step ------------------------------------------------------------
+    @_on_device
     def set_params(self, **params):
         """Updates the given parameters; the others keep their values."""
         new = dict(self.params, **params)
@@ -257,6 +269,7 @@ class LB:
         _check(self.lib.lb_set_params(self.ctx, ctypes.byref(par)))
         self.params, self.par = new, par
 
+    @_on_device
     def reinit(self, rho0, ux0, uy0, T0):
         """Restarts from f = f^eq(rho0, u0, T0) on the same workspace."""
         fields = [self.field(a) for a in (rho0, ux0, uy0, T0)]
@@ -267,11 +280,13 @@ class LB:
                                     _ptr(self.workspace), nbytes, self._stream(),
                                     *[_ptr(f) for f in fields], ctypes.byref(self.ctx)))
 
+    @_on_device
     def step(self, n: int = 1):
         """Advances the state by n steps on the current stream (asynchronous)."""
         self._sync_stream()
         _check(self.lib.lb_step(self.ctx, int(n)))
 
+    @_on_device
     def capture(self, n: int = 2, pool=None):
         """Records n (even) fused steps into a CUDA/HIP graph on a side
         stream; graph.replay() then advances this lattice by n steps.
@@ -295,6 +310,7 @@ class LB:
         self._sync_stream()
         return graph
 
+    @_on_device
     def moments(self):
         """(rho, ux, uy, T) of the current state, Eq. (2), FP64 [lx, ly] each."""
         self._sync_stream()
@@ -320,6 +336,7 @@ class LB:
             raise ValueError("%s must be %s of shape %s" % (what, self.state_dtype, shape))
         return t.to(self.device).contiguous()
 
+    @_on_device
     def get_state(self, out=None) -> torch.Tensor:
         """The state in compact form, in the state dtype: [37, lx, ly] (FP64, or
         the shifted FP32 values f - w rho_ref), or [38, lx, ly] FP32 in the
@@ -333,12 +350,14 @@ class LB:
         _check(self.lib.lb_get_state(self.ctx, _ptr(out)))
         return out
 
+    @_on_device
     def set_state(self, f: torch.Tensor):
         """Replaces the state by f (same form and dtype as get_state returns)."""
         self._sync_stream()
         f = self._state_arg(f, "state")
         _check(self.lib.lb_set_state(self.ctx, _ptr(f)))
 
+    @_on_device
     def populations(self) -> torch.Tensor:
         """The populations f as FP64 [37, lx, ly], in every precision form."""
         self._sync_stream()
@@ -347,26 +366,31 @@ class LB:
         return out
 
     # -- split stages ----------------------------------------------------------
+    @_on_device
     def halo(self):
         """Refreshes the periodic halos of the state (split path)."""
         self._sync_stream()
         _check(self.lib.lb_halo(self.ctx))
 
+    @_on_device
     def propagate(self):
         """Split path: scratch = propagate(state) (needs valid halos)."""
         self._sync_stream()
         _check(self.lib.lb_propagate(self.ctx))
 
+    @_on_device
     def bc(self):
         """Split path: the thermal walls applied to the scratch buffer."""
         self._sync_stream()
         _check(self.lib.lb_bc(self.ctx))
 
+    @_on_device
     def collide(self):
         """Split path: state = collide(scratch)."""
         self._sync_stream()
         _check(self.lib.lb_collide(self.ctx))
 
+    @_on_device
     def get_scratch(self) -> torch.Tensor:
         """The scratch buffer in compact [37, lx, ly] form (state dtype)."""
         self._sync_stream()
@@ -374,6 +398,7 @@ class LB:
         _check(self.lib.lb_get_scratch(self.ctx, _ptr(out)))
         return out
 
+    @_on_device
     def set_scratch(self, f: torch.Tensor):
         """Replaces the scratch buffer by f (compact form, state dtype)."""
         self._sync_stream()
@@ -381,6 +406,7 @@ class LB:
         _check(self.lib.lb_set_scratch(self.ctx, _ptr(f)))
 
     # -- in-situ observables ------------------------------------------------
+    @_on_device
     def observables(self):
         """(profiles [6, ly], scalars [4]) of the current state, on the device."""
         self._sync_stream()
@@ -389,6 +415,7 @@ class LB:
         _check(self.lib.lb_observables(self.ctx, _ptr(prof), _ptr(sc)))
         return prof, sc
 
+    @_on_device
     def run_observed(self, n: int, every: int) -> torch.Tensor:
         """n steps; the 4 scalars after every `every` steps, [n // every, 4]."""
         if int(every) <= 0 or int(n) < 0:
@@ -404,6 +431,7 @@ class LB:
         """An uninitialised tape for n steps: FP64 [n, 4, lx, ly]."""
         return torch.empty((n, 4, self.lx, self.ly), dtype=torch.float64, device=self.device)
 
+    @_on_device
     def step_record(self, n: int, tape: torch.Tensor):
         """n fused steps, writing the pre-collision moments (rho, j_x, j_y,
         sum |c|^2 f) of step j to tape[j] (FP64 lattices only)."""
@@ -414,6 +442,7 @@ class LB:
         self._expect(tape, tape.shape, torch.float64, "tape")
         _check(self.lib.lb_step_record(self.ctx, int(n), _ptr(tape)))
 
+    @_on_device
     def loss_ke(self, with_lambda: bool = True):
         """(KE [1], dKE/df or None) of the current state on the device; dKE/df
         is an adjoint array in this lattice's layout."""
@@ -423,6 +452,7 @@ class LB:
         _check(self.lib.lb_loss_ke(self.ctx, _ptr(ke), _ptr(lam)))
         return ke, lam
 
+    @_on_device
     def adjoint_step(self, tape_j: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor):
         """One transposed step: lam_out = J_j^T lam_in for the step whose
         moments are tape_j (scatter form, lb_adjoint_step)."""
@@ -432,6 +462,7 @@ class LB:
         self._sync_stream()
         _check(self.lib.lb_adjoint_step(self.ctx, _ptr(tape_j), _ptr(lam_in), _ptr(lam_out)))
 
+    @_on_device
     def adjoint_run(self, tape: torch.Tensor, lam: torch.Tensor, n: int = None):
         """n transposed steps (default: all of the tape), lambda^n -> lambda^0
         in place in `lam`, in the gather form (lb_adjoint_run); the padded
@@ -451,6 +482,7 @@ class LB:
                                        self._adj_ws.numel()))
         return lam
 
+    @_on_device
     def adjoint_run_static(self, tape: torch.Tensor, lam: torch.Tensor, n: int = None):
         """As adjoint_run, through lb_adjoint_run_static: no workspace, the
         library's per-GPU 64 MiB scratch (small lattices only; calls that
@@ -465,6 +497,7 @@ class LB:
         _check(self.lib.lb_adjoint_run_static(self.ctx, n, _ptr(tape), _ptr(lam)))
         return lam
 
+    @_on_device
     def init_adjoint(self, rho0, ux0, uy0, T0, lam0: torch.Tensor):
         """dL/d(rho0, ux0, uy0, T0) of f^0 = f^eq(rho0, u0, T0) given lam0 = dL/df^0;
         four FP64 [lx, ly] tensors."""
