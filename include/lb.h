@@ -178,10 +178,12 @@ int lb_step(lb_ctx* ctx, int n);
  * ctx), LB_E_HIP. */
 int lb_moments(lb_ctx* ctx, double* rho, double* ux, double* uy, double* T);
 
-/* Device copies of the state in compact form [37][lx][ly]: double for
- * LB_FP64, float g_l = f_l - w_l rho_ref for the FP32 modes.  set_state
- * refreshes the halos.  Used for checkpoints.  Errors: LB_E_ARG (NULL
- * pointers), LB_E_HIP. */
+/* Device copies of the state in compact form: [37][lx][ly] double for
+ * LB_FP64, [37][lx][ly] float g_l = f_l - w_l rho_ref for the shifted FP32
+ * modes, and [38][lx][ly] 32-bit words for LB_FP32_COLLIDE / LB_FP32_LOCAL
+ * (37 float deviations, then each site's packed FP16 reference, rho_s low,
+ * th_s high).  set_state refreshes the halos.  Used for checkpoints.
+ * Errors: LB_E_ARG (NULL pointers), LB_E_HIP. */
 int lb_get_state(lb_ctx* ctx, void* f);
 int lb_set_state(lb_ctx* ctx, const void* f);
 
@@ -200,7 +202,9 @@ int lb_get_populations(lb_ctx* ctx, double* f);
  * lb_propagate and lb_collide run the alternative kernel of the context's
  * LB_KERNEL_SPLIT_* value where it names one (lb_step's split path too).
  * lb_get_scratch / lb_set_scratch copy B's physical region in the compact
- * form of lb_get_state. */
+ * form of lb_get_state.  The local-reference forms (LB_FP32_COLLIDE,
+ * LB_FP32_LOCAL) have no split stages: lb_propagate, lb_bc, lb_collide,
+ * lb_get_scratch and lb_set_scratch return LB_E_STATE for them. */
 int lb_halo(lb_ctx* ctx);
 int lb_propagate(lb_ctx* ctx);
 int lb_bc(lb_ctx* ctx);
